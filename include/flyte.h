@@ -1,0 +1,211 @@
+/*
+ * flyte.h -- C ABI of libflyte, multibyte ("flyte") floating point on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Storage format (Anderson & Gregg, "Vectorization of Multibyte Floating
+ * Point Data Formats", PACT 2016, Section 3.1 and Table 1): a value derived
+ * from an IEEE-754 base type (binary32 or binary64) keeps the sign and the
+ * full exponent field of that type and the top m = 8k - 1 - E bits of its
+ * mantissa, so it is stored in k bytes: binary32 with k = 2, 3, 4 (4 is
+ * binary32 itself; 2 is bit-for-bit bfloat16) and binary64 with k = 2..8
+ * (5, 6, 7 are the paper's 40-, 48- and 56-bit formats; 8 is binary64).
+ *
+ * Packed arrays (Section 4.1): element i occupies bytes [i*k, i*k + k) with no
+ * padding; those bytes are the top k bytes of the little-endian base bit
+ * pattern, in little-endian order.  Matrices are row-major; a leading
+ * dimension (lda, ldb, ldc) counts elements, and row r starts at byte
+ * r*ld*k.
+ *
+ * Conversion: unpack shifts the k bytes to the top of the base word and fills
+ * the dropped bytes with zeros (Section 3.2).  pack rounds to nearest, ties to
+ * even, at the cut (Section 5.2), with the increment carrying into the
+ * exponent: values round up into the next binade, the largest finite values
+ * can round to infinity, subnormals underflow gradually (Section 5.3).  A NaN
+ * is truncated and, if that leaves its kept mantissa zero, gets the quiet bit
+ * (the top kept mantissa bit), so NaN stays NaN with its sign.  Denormals are
+ * never flushed.
+ *
+ * Arithmetic (Section 3.1, and the AT_LEAST accumulator and FP_CONTRACT of
+ * Section 4.4): every operation computes in the base type -- binary32 formats
+ * in FP32, binary64 formats in FP64 -- with fused multiply-adds; accumulators
+ * are held in the base type.  The GEMMs are the exception, see fb_gemm.
+ *
+ * Conventions for every call:
+ *  - "native" means float for base 32 and double for base 64.
+ *  - All data pointers are DEVICE pointers owned by the caller.  Every
+ *    pointer must be 4-byte aligned, and every packed matrix row must start on
+ *    a 4-byte boundary ((ld*k) % 4 == 0); otherwise FB_ERR_ALIGN.  Kernels use
+ *    wider accesses when pointers and rows are 16-byte aligned.
+ *  - All calls are asynchronous on `stream` (0 = the null stream).  Argument
+ *    errors are detected on the host, return immediately and launch nothing.
+ *    A launch failure returns FB_ERR_RUNTIME.  Details of the last error on
+ *    the calling thread are in fb_last_error().
+ *  - n = 0 (or m = 0) is valid and launches nothing (fb_dot writes 0).
+ *  - Nothing aborts, throws or prints.  Hot calls allocate no device memory,
+ *    except fb_dot's per-(device, stream) partial-sum buffer (16 KiB), which
+ *    is allocated on the first fb_dot call on that stream and kept.
+ *  - Input and output ranges must not overlap unless a call says so.
+ */
+#ifndef FLYTE_H
+#define FLYTE_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Format descriptor {base, k}: base 32 with k in 2..4, or base 64 with k in 2..8. */
+typedef struct fb_format {
+    uint8_t base;
+    uint8_t k;
+} fb_format;
+
+typedef enum fb_status {
+    FB_OK = 0,
+    FB_ERR_FORMAT = 1,       /* {base, k} is not a flyte format */
+    FB_ERR_ARG = 2,          /* null pointer, negative size, bad leading dimension */
+    FB_ERR_ALIGN = 3,        /* pointer or row start not 4-byte aligned */
+    FB_ERR_UNSUPPORTED = 4,  /* valid formats, but no kernel for this combination */
+    FB_ERR_RUNTIME = 5       /* HIP runtime error (launch, allocation, graph) */
+} fb_status;
+
+/* ------------------------------------------------------------------ codec */
+
+/* Pack n native values into n k-byte elements (Sections 5.2 and 5.3).
+ * src_native: n floats/doubles; dst_packed: n*k bytes.  Bit-exact. */
+fb_status fb_pack(fb_format f, const void *src_native, void *dst_packed, size_t n,
+                  hipStream_t stream);
+
+/* Unpack n k-byte elements into n native values (Sections 3.2 and 4.1).
+ * src_packed: n*k bytes; dst_native: n floats/doubles.  Bit-exact. */
+fb_status fb_unpack(fb_format f, const void *src_packed, void *dst_native, size_t n,
+                    hipStream_t stream);
+
+/* ------------------------------------------------------------------ BLAS 1 */
+
+/* result = sum_i unpack(x_i) * unpack(y_i), x and y packed (n*k bytes each).
+ * Products and sums in the base type with fma; the reduction order is fixed
+ * (per-thread sequential, then fixed trees), so repeated calls on the same
+ * device give identical bits.  result: one native value in device memory. */
+fb_status fb_dot(fb_format f, size_t n, const void *x, const void *y, void *result,
+                 hipStream_t stream);
+
+/* y_i <- pack(fma(alpha, unpack(x_i), unpack(y_i))), in place on y.
+ * alpha is first rounded to the native type.  Bit-exact per element.
+ * x and y are packed (n*k bytes); x must not overlap y. */
+fb_status fb_axpy(fb_format f, size_t n, double alpha, const void *x, void *y,
+                  hipStream_t stream);
+
+/* ------------------------------------------------------------------ BLAS 2 */
+
+/* y = A x.  A: m x n packed, row-major, leading dimension lda >= n (elements).
+ * x: n native values; y: m native values.  Each y_r is a sequence of fmas in
+ * the base type in an order fixed by the tile configuration (chosen by the
+ * autotuner cache, else a default for the shape). */
+fb_status fb_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
+                  const void *x, void *y, hipStream_t stream);
+
+/* Same as fb_gemv with the tile configuration forced: config is an index in
+ * [0, fb_gemv_num_configs()).  Used by the autotuner and for reproducibility. */
+fb_status fb_gemv_config(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
+                         const void *x, void *y, int32_t config, hipStream_t stream);
+
+/* Number of GEMV tile configurations, and a description of one
+ * (rows per wave, waves per block, chunks in flight per lane; returns 0 if
+ * config is out of range). */
+int32_t fb_gemv_num_configs(void);
+int32_t fb_gemv_config_info(int32_t config, int32_t *rows_per_wave, int32_t *waves_per_block,
+                            int32_t *chunks_per_lane);
+
+/* ------------------------------------------------------------------ autotuner */
+
+/* Times every GEMV tile configuration on the caller's buffers (A, x, y as for
+ * fb_gemv; y is overwritten) with `reps` timed launches each on `stream`,
+ * records the fastest for the (format, shape bucket) in the in-process cache,
+ * and returns its index in *best (may be NULL).  Synchronises the stream. */
+fb_status fb_tune_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
+                       const void *x, void *y, int32_t reps, int32_t *best, hipStream_t stream);
+
+/* The cached choice for (format, m, n), or -1 if none. */
+int32_t fb_tune_lookup(fb_format f, int64_t m, int64_t n);
+
+/* Saves / loads the tile cache as JSON (path NULL: $FLYTE_TUNE_CACHE).
+ * Loading merges into the in-process cache. */
+fb_status fb_tune_save(const char *path);
+fb_status fb_tune_load(const char *path);
+void fb_tune_clear(void);
+
+/* ------------------------------------------------------------------ batched GEMV */
+
+/* One independent GEMV y = A x of a batch (same semantics as fb_gemv). */
+typedef struct fb_gemv_desc {
+    fb_format f;
+    uint16_t reserved0;
+    int32_t m;
+    int32_t n;
+    int32_t reserved1;
+    int64_t lda;
+    const void *A;
+    const void *x;
+    void *y;
+} fb_gemv_desc;   /* 48 bytes */
+
+typedef struct fb_plan fb_plan;
+
+/* Validates `count` descriptors (host array), picks a tile configuration per
+ * descriptor from the autotuner cache, orders the work, and uploads a device
+ * work table.  The plan owns that table and its work counter; the descriptor
+ * array may be freed afterwards.  Buffers named by the descriptors must stay
+ * valid while the plan is launched.  Distinct descriptors must not share y. */
+fb_status fb_gemv_batched_plan(const fb_gemv_desc *descs, int32_t count, fb_plan **out);
+
+/* Runs every GEMV of the plan in ONE persistent kernel: workgroups take
+ * (descriptor, row tile) work items from a device counter until none remain.
+ * The first launch on a stream captures a HIP graph (counter reset + kernel);
+ * later launches on that stream replay it.  Each y equals fb_gemv_config on
+ * the same descriptor with the plan's configuration, bit for bit. */
+fb_status fb_gemv_batched_launch(fb_plan *plan, hipStream_t stream);
+
+/* Reference schedule: one fb_gemv_config launch per descriptor, in order. */
+fb_status fb_gemv_batched_loop(fb_plan *plan, hipStream_t stream);
+
+/* Algorithmic bytes of the plan (sum of m*n*k + native bytes of x and y). */
+int64_t fb_plan_bytes(const fb_plan *plan);
+/* Tile configuration chosen for descriptor i (or -1). */
+int32_t fb_plan_config(const fb_plan *plan, int32_t i);
+
+/* Frees the plan's device memory and graphs (synchronises its streams). */
+void fb_plan_destroy(fb_plan *plan);
+
+/* ------------------------------------------------------------------ BLAS 3 */
+
+/* C = A B with A M x K (lda), B K x N (ldb), C M x N (ldc), row-major.
+ * Supported combinations (others: FB_ERR_UNSUPPORTED):
+ *  - fa = fb = {32,2}, fc = {32,4}: the stored 2-byte patterns are bfloat16
+ *    operands of BF16 matrix-core instructions, FP32 accumulation, FP32 C.
+ *  - fa = fb = {32,3}, fc = {32,4}: each operand is split while loading into
+ *    hi = its top two bytes (a bfloat16) and lo = x - hi (exact, and exactly a
+ *    bfloat16 for normal x with biased exponent >= 9); C = hi*hi + hi*lo +
+ *    lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
+ *  - fa = fb = {64,5} or {64,6}, fc any binary64 format: operands unpacked to
+ *    FP64, FP64 matrix-core products and accumulation, C rounded to fc in the
+ *    epilogue (one rounding of the FP64 result, Section 5.2).
+ * M, N, K >= 0; M and N must be multiples of 4 for a packed C with k < 8. */
+fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
+                  const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
+                  hipStream_t stream);
+
+/* ------------------------------------------------------------------ errors */
+
+const char *fb_status_str(fb_status status);
+/* Detail of the last failing call on this thread ("" if none). */
+const char *fb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLYTE_H */

@@ -1,0 +1,344 @@
+// Streaming kernels over packed arrays: pack, unpack, axpy and dot.
+//
+// Every kernel walks the array in units of F::UNIT elements (whole dwords of
+// packed data).  Thread t of a grid of T threads handles units t, t + T, ...,
+// U of them per loop trip, so each wave-wide memory instruction touches one
+// contiguous span.  The fewer than UNIT elements after the last whole unit are
+// handled one by one with byte accesses by the first threads of block 0.
+#include <mutex>
+#include <map>
+
+#include "codec.hpp"
+#include "common.hpp"
+
+namespace flyte {
+
+constexpr int kBlock = 256;
+constexpr int kUnroll = 4;
+
+// ---------------------------------------------------------------- pack
+template <class F, int U>
+__global__ void __launch_bounds__(kBlock)
+k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
+{
+    using T = typename F::bits_t;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
+        uint32_t w[U][F::UNIT_NW];
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) load_dwords(src + g * F::UNIT_NW, w[u]);
+        });
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                T b[F::UNIT];
+                words_to_bits<F, F::UNIT>(w[u], b);
+#pragma unroll
+                for (int e = 0; e < F::UNIT; ++e) b[e] = rne_pack<F>(b[e]);
+                uint32_t P[F::UNIT_DW];
+                assemble_elems<F, F::UNIT>(b, P);
+                store_dwords(dst + g * F::UNIT_DW, P);
+            }
+        });
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nunits * F::UNIT + threadIdx.x;
+        if (threadIdx.x < F::UNIT && i < n) {
+            T u;
+            if constexpr (F::W == 4) u = src[i];
+            else u = (uint64_t(src[2 * i + 1]) << 32) | src[2 * i];
+            store_elem_bytes<F>(reinterpret_cast<uint8_t*>(dst) + i * F::k, rne_pack<F>(u));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- unpack
+template <class F, int U>
+__global__ void __launch_bounds__(kBlock)
+k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
+{
+    using T = typename F::bits_t;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
+        uint32_t P[U][F::UNIT_DW];
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) load_dwords(src + g * F::UNIT_DW, P[u]);
+        });
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                T b[F::UNIT];
+                unpack_elems<F, F::UNIT>(P[u], b);
+                uint32_t w[F::UNIT_NW];
+                bits_to_words<F, F::UNIT>(b, w);
+                store_dwords(dst + g * F::UNIT_NW, w);
+            }
+        });
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nunits * F::UNIT + threadIdx.x;
+        if (threadIdx.x < F::UNIT && i < n) {
+            const T u = load_elem_unpacked<F>(reinterpret_cast<const uint8_t*>(src) + i * F::k);
+            if constexpr (F::W == 4) {
+                dst[i] = u;
+            } else {
+                dst[2 * i] = uint32_t(u);
+                dst[2 * i + 1] = uint32_t(u >> 32);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- axpy
+template <class F, int U>
+__global__ void __launch_bounds__(kBlock)
+k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __restrict__ y, int64_t nunits,
+       int64_t n)
+{
+    using T = typename F::bits_t;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
+        uint32_t PX[U][F::UNIT_DW], PY[U][F::UNIT_DW];
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                load_dwords(x + g * F::UNIT_DW, PX[u]);
+                load_dwords(y + g * F::UNIT_DW, PY[u]);
+            }
+        });
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                T bx[F::UNIT], by[F::UNIT];
+                unpack_elems<F, F::UNIT>(PX[u], bx);
+                unpack_elems<F, F::UNIT>(PY[u], by);
+#pragma unroll
+                for (int e = 0; e < F::UNIT; ++e)
+                    by[e] = rne_pack<F>(as_bits<F>(fma_n(alpha, as_native<F>(bx[e]), as_native<F>(by[e]))));
+                uint32_t P[F::UNIT_DW];
+                assemble_elems<F, F::UNIT>(by, P);
+                store_dwords(y + g * F::UNIT_DW, P);
+            }
+        });
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nunits * F::UNIT + threadIdx.x;
+        if (threadIdx.x < F::UNIT && i < n) {
+            const uint8_t* xb = reinterpret_cast<const uint8_t*>(x) + i * F::k;
+            uint8_t* yb = reinterpret_cast<uint8_t*>(y) + i * F::k;
+            const auto r = fma_n(alpha, as_native<F>(load_elem_unpacked<F>(xb)),
+                                 as_native<F>(load_elem_unpacked<F>(yb)));
+            store_elem_bytes<F>(yb, rne_pack<F>(as_bits<F>(r)));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dot
+template <class T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+    // xor butterfly: every lane ends with the same, order-fixed total
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = v + __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v)
+{
+    __shared__ T part[kBlock / 64];
+    v = wave_sum(v);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    T s = T(0);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) s = s + part[w];
+    return s;
+}
+
+template <class F, int U>
+__global__ void __launch_bounds__(kBlock)
+k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, int64_t nunits, int64_t n,
+              typename F::native_t* __restrict__ partials)
+{
+    using T = typename F::bits_t;
+    using N = typename F::native_t;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    N acc = N(0);
+    for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
+        uint32_t PX[U][F::UNIT_DW], PY[U][F::UNIT_DW];
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                load_dwords(x + g * F::UNIT_DW, PX[u]);
+                load_dwords(y + g * F::UNIT_DW, PY[u]);
+            }
+        });
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                T bx[F::UNIT], by[F::UNIT];
+                unpack_elems<F, F::UNIT>(PX[u], bx);
+                unpack_elems<F, F::UNIT>(PY[u], by);
+#pragma unroll
+                for (int e = 0; e < F::UNIT; ++e) acc = fma_n(as_native<F>(bx[e]), as_native<F>(by[e]), acc);
+            }
+        });
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nunits * F::UNIT + threadIdx.x;
+        if (threadIdx.x < F::UNIT && i < n) {
+            acc = fma_n(as_native<F>(load_elem_unpacked<F>(reinterpret_cast<const uint8_t*>(x) + i * F::k)),
+                        as_native<F>(load_elem_unpacked<F>(reinterpret_cast<const uint8_t*>(y) + i * F::k)), acc);
+        }
+    }
+    const N s = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <class N>
+__global__ void __launch_bounds__(kBlock) k_dot_final(const N* __restrict__ partials, int nparts, N* __restrict__ out)
+{
+    N acc = N(0);
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc = acc + partials[i];
+    const N s = block_sum(acc);
+    if (threadIdx.x == 0) *out = s;
+}
+
+template <class N>
+__global__ void k_store_zero(N* out)
+{
+    *out = N(0);
+}
+
+// ---------------------------------------------------------------- host side
+constexpr int kMaxDotBlocks = 2048;
+
+static int stream_grid(int64_t nunits, int unroll)
+{
+    const int64_t per_block = (int64_t)kBlock * unroll;
+    int64_t blocks = (nunits + per_block - 1) / per_block;
+    const int64_t cap = (int64_t)device_cu_count() * 16;
+    if (blocks > cap) blocks = cap;
+    if (blocks < 1) blocks = 1;
+    return (int)blocks;
+}
+
+// Partial-sum buffer for fb_dot, one per (device, stream), kept for the life
+// of the process.
+static fb_status dot_workspace(hipStream_t stream, void** out)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, void*> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(FB_ERR_RUNTIME, "fb_dot: hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(mu);
+    auto key = std::make_pair(dev, stream);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        *out = it->second;
+        return FB_OK;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, kMaxDotBlocks * sizeof(double)) != hipSuccess)
+        return set_error(FB_ERR_RUNTIME, "fb_dot: workspace allocation failed");
+    cache[key] = p;
+    *out = p;
+    return FB_OK;
+}
+
+static fb_status check_vec(const char* what, fb_format f, const void* a, const void* b, size_t n)
+{
+    if (!format_ok(f)) return set_error(FB_ERR_FORMAT, "%s: invalid format {%d,%d}", what, f.base, f.k);
+    if (n > (size_t)INT64_MAX / 16) return set_error(FB_ERR_ARG, "%s: n too large", what);
+    if (n == 0) return FB_OK;
+    if (!a || !b) return set_error(FB_ERR_ARG, "%s: null pointer", what);
+    if (!aligned4(a) || !aligned4(b)) return set_error(FB_ERR_ALIGN, "%s: pointers must be 4-byte aligned", what);
+    return FB_OK;
+}
+
+}  // namespace flyte
+
+using namespace flyte;
+
+extern "C" fb_status fb_pack(fb_format f, const void* src_native, void* dst_packed, size_t n, hipStream_t stream)
+{
+    fb_status st = check_vec("fb_pack", f, src_native, dst_packed, n);
+    if (st != FB_OK || n == 0) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        k_pack<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+            static_cast<const uint32_t*>(src_native), static_cast<uint32_t*>(dst_packed), nunits, (int64_t)n);
+        return check_launch("fb_pack");
+    });
+}
+
+extern "C" fb_status fb_unpack(fb_format f, const void* src_packed, void* dst_native, size_t n, hipStream_t stream)
+{
+    fb_status st = check_vec("fb_unpack", f, src_packed, dst_native, n);
+    if (st != FB_OK || n == 0) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        k_unpack<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+            static_cast<const uint32_t*>(src_packed), static_cast<uint32_t*>(dst_native), nunits, (int64_t)n);
+        return check_launch("fb_unpack");
+    });
+}
+
+extern "C" fb_status fb_axpy(fb_format f, size_t n, double alpha, const void* x, void* y, hipStream_t stream)
+{
+    fb_status st = check_vec("fb_axpy", f, x, y, n);
+    if (st != FB_OK || n == 0) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        using N = typename F::native_t;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        k_axpy<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+            (N)alpha, static_cast<const uint32_t*>(x), static_cast<uint32_t*>(y), nunits, (int64_t)n);
+        return check_launch("fb_axpy");
+    });
+}
+
+extern "C" fb_status fb_dot(fb_format f, size_t n, const void* x, const void* y, void* result, hipStream_t stream)
+{
+    if (!result) return set_error(FB_ERR_ARG, "fb_dot: null result");
+    if (!aligned4(result)) return set_error(FB_ERR_ALIGN, "fb_dot: result must be 4-byte aligned");
+    fb_status st = check_vec("fb_dot", f, x, y, n);
+    if (st != FB_OK) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        using N = typename F::native_t;
+        if (n == 0) {
+            k_store_zero<N><<<1, 1, 0, stream>>>(static_cast<N*>(result));
+            return check_launch("fb_dot");
+        }
+        void* ws = nullptr;
+        fb_status s2 = dot_workspace(stream, &ws);
+        if (s2 != FB_OK) return s2;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        int grid = stream_grid(nunits, kUnroll);
+        if (grid > kMaxDotBlocks) grid = kMaxDotBlocks;
+        k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
+                                                               static_cast<const uint32_t*>(y), nunits,
+                                                               (int64_t)n, static_cast<N*>(ws));
+        k_dot_final<N><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
+        return check_launch("fb_dot");
+    });
+}

@@ -1,0 +1,56 @@
+// Status strings, per-thread error detail, and small device queries.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <unordered_map>
+
+#include "common.hpp"
+
+namespace flyte {
+
+static thread_local char g_last_error[512] = "";
+
+fb_status set_error(fb_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+void clear_error() { g_last_error[0] = '\0'; }
+
+int device_cu_count()
+{
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
+
+}  // namespace flyte
+
+extern "C" const char* fb_status_str(fb_status status)
+{
+    switch (status) {
+        case FB_OK: return "FB_OK";
+        case FB_ERR_FORMAT: return "FB_ERR_FORMAT";
+        case FB_ERR_ARG: return "FB_ERR_ARG";
+        case FB_ERR_ALIGN: return "FB_ERR_ALIGN";
+        case FB_ERR_UNSUPPORTED: return "FB_ERR_UNSUPPORTED";
+        case FB_ERR_RUNTIME: return "FB_ERR_RUNTIME";
+    }
+    return "FB_ERR_UNKNOWN";
+}
+
+extern "C" const char* fb_last_error(void) { return flyte::g_last_error; }

@@ -1,0 +1,278 @@
+"""Python binding of libflyte (the C ABI of ``include/flyte.h``).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+``libflyte.so``.  PyTorch supplies device memory (packed arrays are ``uint8``
+tensors of n*k bytes) and the current stream.  If the library is missing it is
+built with hipcc; if that fails, every call raises -- there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+
+import torch
+
+from . import build as _build
+
+FORMATS = [(32, 2), (32, 3), (32, 4)] + [(64, k) for k in range(2, 9)]
+
+FB_OK, FB_ERR_FORMAT, FB_ERR_ARG, FB_ERR_ALIGN, FB_ERR_UNSUPPORTED, FB_ERR_RUNTIME = range(6)
+
+
+class FlyteError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{status_name(status)}: {detail}")
+        self.status = status
+
+
+class fb_format(ctypes.Structure):
+    _fields_ = [("base", ctypes.c_uint8), ("k", ctypes.c_uint8)]
+
+
+class fb_gemv_desc(ctypes.Structure):
+    _fields_ = [("f", fb_format), ("reserved0", ctypes.c_uint16), ("m", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("reserved1", ctypes.c_int32), ("lda", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+assert ctypes.sizeof(fb_gemv_desc) == 48
+
+_lock = threading.Lock()
+_lib = None
+
+_P, _I32, _I64, _SZ, _DBL = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+_SIGS = {
+    "fb_pack": (_I32, [fb_format, _P, _P, _SZ, _P]),
+    "fb_unpack": (_I32, [fb_format, _P, _P, _SZ, _P]),
+    "fb_dot": (_I32, [fb_format, _SZ, _P, _P, _P, _P]),
+    "fb_axpy": (_I32, [fb_format, _SZ, _DBL, _P, _P, _P]),
+    "fb_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _P]),
+    "fb_gemv_config": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, _P]),
+    "fb_gemv_num_configs": (_I32, []),
+    "fb_gemv_config_info": (_I32, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "fb_tune_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, ctypes.POINTER(_I32), _P]),
+    "fb_tune_lookup": (_I32, [fb_format, _I64, _I64]),
+    "fb_tune_save": (_I32, [ctypes.c_char_p]),
+    "fb_tune_load": (_I32, [ctypes.c_char_p]),
+    "fb_tune_clear": (None, []),
+    "fb_gemv_batched_plan": (_I32, [ctypes.POINTER(fb_gemv_desc), _I32, ctypes.POINTER(_P)]),
+    "fb_gemv_batched_launch": (_I32, [_P, _P]),
+    "fb_gemv_batched_loop": (_I32, [_P, _P]),
+    "fb_plan_bytes": (_I64, [_P]),
+    "fb_plan_config": (_I32, [_P, _I32]),
+    "fb_plan_destroy": (None, [_P]),
+    "fb_gemm": (_I32, [fb_format, fb_format, fb_format, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "fb_status_str": (ctypes.c_char_p, [_I32]),
+    "fb_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def load() -> ctypes.CDLL:
+    """Loads libflyte.so (building it first if it is absent)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = lib_path()
+            if not os.path.exists(path):
+                _build.build()
+            if not os.path.exists(path):
+                raise RuntimeError(f"libflyte.so is missing at {path} and could not be built")
+            lib = ctypes.CDLL(path)
+            for name, (res, args) in _SIGS.items():
+                fn = getattr(lib, name, None)
+                if fn is None:
+                    continue
+                fn.restype = res
+                fn.argtypes = args
+            _lib = lib
+        return _lib
+
+
+def status_name(status: int) -> str:
+    return load().fb_status_str(status).decode()
+
+
+def last_error() -> str:
+    return load().fb_last_error().decode()
+
+
+def _check(status: int) -> None:
+    if status != FB_OK:
+        raise FlyteError(status, last_error())
+
+
+def fmt(base_k) -> fb_format:
+    base, k = base_k
+    return fb_format(base, k)
+
+
+def native_dtype(base: int) -> torch.dtype:
+    return torch.float32 if base == 32 else torch.float64
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+# ---------------------------------------------------------------- codec
+def pack(f, src: torch.Tensor, out: torch.Tensor | None = None, n: int | None = None, stream=None):
+    """Rounds native values (float32 for base 32, float64 for base 64) to k-byte elements."""
+    base, k = f
+    n = src.numel() if n is None else n
+    if out is None:
+        out = torch.empty(n * k, dtype=torch.uint8, device=src.device)
+    _check(load().fb_pack(fmt(f), _ptr(src), _ptr(out), n, _stream(stream)))
+    return out
+
+
+def unpack(f, packed: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None, stream=None):
+    base, k = f
+    n = packed.numel() // k if n is None else n
+    if out is None:
+        out = torch.empty(n, dtype=native_dtype(base), device=packed.device)
+    _check(load().fb_unpack(fmt(f), _ptr(packed), _ptr(out), n, _stream(stream)))
+    return out
+
+
+# ---------------------------------------------------------------- BLAS 1
+def dot(f, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None, stream=None):
+    base, k = f
+    n = x.numel() // k if n is None else n
+    if out is None:
+        out = torch.empty((), dtype=native_dtype(base), device=x.device)
+    _check(load().fb_dot(fmt(f), n, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
+    return out
+
+
+def axpy(f, alpha: float, x: torch.Tensor, y: torch.Tensor, n: int | None = None, stream=None):
+    """y <- pack(alpha * x + y), in place on the packed tensor y."""
+    base, k = f
+    n = y.numel() // k if n is None else n
+    _check(load().fb_axpy(fmt(f), n, float(alpha), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+# ---------------------------------------------------------------- BLAS 2
+def gemv(f, A: torch.Tensor, m: int, n: int, x: torch.Tensor, y: torch.Tensor | None = None,
+         lda: int | None = None, config: int | None = None, stream=None):
+    base, k = f
+    lda = n if lda is None else lda
+    if y is None:
+        y = torch.empty(m, dtype=native_dtype(base), device=A.device)
+    if config is None:
+        _check(load().fb_gemv(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), _stream(stream)))
+    else:
+        _check(load().fb_gemv_config(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), config, _stream(stream)))
+    return y
+
+
+def gemv_num_configs() -> int:
+    return load().fb_gemv_num_configs()
+
+
+def gemv_config_info(config: int):
+    rpw, wpb, cpl = _I32(), _I32(), _I32()
+    lpr = load().fb_gemv_config_info(config, ctypes.byref(rpw), ctypes.byref(wpb), ctypes.byref(cpl))
+    return {"lanes_per_row": lpr, "rows_per_wave": rpw.value, "waves_per_block": wpb.value,
+            "units_per_lane": cpl.value}
+
+
+def tune_gemv(f, A, m, n, x, y, lda=None, reps: int = 10, stream=None) -> int:
+    lda = n if lda is None else lda
+    best = _I32(-1)
+    _check(load().fb_tune_gemv(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), reps, ctypes.byref(best),
+                               _stream(stream)))
+    return best.value
+
+
+def tune_lookup(f, m, n) -> int:
+    return load().fb_tune_lookup(fmt(f), m, n)
+
+
+def tune_save(path: str) -> None:
+    _check(load().fb_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _check(load().fb_tune_load(path.encode()))
+
+
+def tune_clear() -> None:
+    load().fb_tune_clear()
+
+
+# ---------------------------------------------------------------- batched GEMV
+@dataclass
+class GemvItem:
+    f: tuple
+    m: int
+    n: int
+    lda: int
+    A: torch.Tensor
+    x: torch.Tensor
+    y: torch.Tensor
+
+
+class BatchedGemv:
+    """A plan for many independent GEMVs run by one persistent kernel."""
+
+    def __init__(self, items: list[GemvItem]):
+        self.items = items               # keeps the tensors alive
+        arr = (fb_gemv_desc * max(1, len(items)))()
+        for i, it in enumerate(items):
+            arr[i] = fb_gemv_desc(fmt(it.f), 0, it.m, it.n, 0, it.lda, _ptr(it.A), _ptr(it.x), _ptr(it.y))
+        plan = _P()
+        _check(load().fb_gemv_batched_plan(arr, len(items), ctypes.byref(plan)))
+        self._plan = plan
+
+    def launch(self, stream=None) -> None:
+        _check(load().fb_gemv_batched_launch(self._plan, _stream(stream)))
+
+    def loop(self, stream=None) -> None:
+        _check(load().fb_gemv_batched_loop(self._plan, _stream(stream)))
+
+    @property
+    def nbytes(self) -> int:
+        return load().fb_plan_bytes(self._plan)
+
+    def config(self, i: int) -> int:
+        return load().fb_plan_config(self._plan, i)
+
+    def close(self) -> None:
+        if self._plan:
+            load().fb_plan_destroy(self._plan)
+            self._plan = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- BLAS 3
+def gemm(fa, fb, fc, M: int, N: int, K: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
+         lda: int | None = None, ldb: int | None = None, ldc: int | None = None, stream=None):
+    lda = K if lda is None else lda
+    ldb = N if ldb is None else ldb
+    ldc = N if ldc is None else ldc
+    if C is None:
+        if fc[1] * 8 == fc[0]:
+            C = torch.empty(M * ldc, dtype=native_dtype(fc[0]), device=A.device)
+        else:
+            C = torch.empty(M * ldc * fc[1], dtype=torch.uint8, device=A.device)
+    _check(load().fb_gemm(fmt(fa), fmt(fb), fmt(fc), M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
+                          _stream(stream)))
+    return C

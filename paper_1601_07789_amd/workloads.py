@@ -86,6 +86,51 @@ def mixed_binary64(n: int, seed: int) -> np.ndarray:
     return bits
 
 
+def mixed_binary32(n: int, seed: int) -> np.ndarray:
+    """binary32 bit patterns (uint32): 90% N(0,1) * 2^U(-30,30), 10% special values
+    (signed zeros, subnormals, infinities, quiet and signalling NaNs, largest
+    finite magnitudes, and exact ties / near-ties for a random cut k in 2..3)."""
+    g = np.random.default_rng(seed)
+    vals = (g.standard_normal(n) * np.exp2(g.uniform(-30.0, 30.0, n))).astype(np.float32)
+    bits = vals.view(np.uint32).copy()
+    n_spec = n // 10
+    idx = g.permutation(n)[:n_spec]
+    kinds = np.arange(n_spec) % 9
+    g.shuffle(kinds)
+    sign = g.integers(0, 2, n_spec, dtype=np.uint32) << np.uint32(31)
+    mant = g.integers(1, 1 << 23, n_spec, dtype=np.uint32)
+    out = np.empty(n_spec, dtype=np.uint32)
+    for t in range(9):
+        sel = kinds == t
+        cnt = int(sel.sum())
+        s = sign[sel]
+        if t == 0:
+            v = s
+        elif t == 1:
+            v = s | mant[sel]
+        elif t == 2:
+            v = s | np.uint32(0x7F800000)
+        elif t == 3:
+            v = s | np.uint32(0x7FC00000) | (mant[sel] & np.uint32((1 << 22) - 1))
+        elif t == 4:
+            v = s | np.uint32(0x7F800000) | g.integers(1, 1 << 8, cnt, dtype=np.uint32)
+        elif t == 5:
+            v = s | np.uint32(0x7F7FFFFF)
+        else:
+            kk = g.integers(2, 4, cnt)
+            d = (32 - 8 * kk).astype(np.uint32)
+            expo = g.integers(1, 255, cnt, dtype=np.uint32)
+            top = (s | (expo << np.uint32(23)) | mant[sel]) >> d << d
+            v = top | (np.uint32(1) << (d - np.uint32(1)))
+            if t == 7:
+                v = v + np.uint32(1)
+            elif t == 8:
+                v = v - np.uint32(1)
+        out[sel] = v
+    bits[idx] = out
+    return bits
+
+
 def uniform(n: int, seed: int, dtype=np.float64, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(lo, hi, n).astype(dtype)
 
