@@ -132,6 +132,11 @@ fb_status fb_tune_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t
 /* The cached choice for (format, m, n), or -1 if none. */
 int32_t fb_tune_lookup(fb_format f, int64_t m, int64_t n);
 
+/* Records a choice measured by the caller (for example with rotating buffers
+ * so that the 256 MB last-level cache holds none of A) for the shape bucket of
+ * (m, n).  us is the measured time per launch, kept for the saved cache. */
+fb_status fb_tune_record(fb_format f, int64_t m, int64_t n, int32_t config, double us);
+
 /* Saves / loads the tile cache as JSON (path NULL: $FLYTE_TUNE_CACHE).
  * Loading merges into the in-process cache. */
 fb_status fb_tune_save(const char *path);

@@ -182,6 +182,16 @@ extern "C" fb_status fb_tune_gemv(fb_format f, int64_t m, int64_t n, const void*
     return FB_OK;
 }
 
+extern "C" fb_status fb_tune_record(fb_format f, int64_t m, int64_t n, int32_t config, double us)
+{
+    if (!format_ok(f)) return set_error(FB_ERR_FORMAT, "fb_tune_record: invalid format {%d,%d}", f.base, f.k);
+    if (m <= 0 || n <= 0) return set_error(FB_ERR_ARG, "fb_tune_record: empty shape");
+    if (config < 0 || config >= kGemvNumTiles) return set_error(FB_ERR_ARG, "fb_tune_record: bad config %d", config);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{f.base, f.k, bucket(m), bucket(n)}] = {config, us};
+    return FB_OK;
+}
+
 static const char* cache_path(const char* path)
 {
     if (path && *path) return path;

@@ -54,6 +54,7 @@ _SIGS = {
     "fb_gemv_config_info": (_I32, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "fb_tune_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, ctypes.POINTER(_I32), _P]),
     "fb_tune_lookup": (_I32, [fb_format, _I64, _I64]),
+    "fb_tune_record": (_I32, [fb_format, _I64, _I64, _I32, _DBL]),
     "fb_tune_save": (_I32, [ctypes.c_char_p]),
     "fb_tune_load": (_I32, [ctypes.c_char_p]),
     "fb_tune_clear": (None, []),
@@ -199,6 +200,10 @@ def tune_gemv(f, A, m, n, x, y, lda=None, reps: int = 10, stream=None) -> int:
 
 def tune_lookup(f, m, n) -> int:
     return load().fb_tune_lookup(fmt(f), m, n)
+
+
+def tune_record(f, m, n, config: int, us: float) -> None:
+    _check(load().fb_tune_record(fmt(f), m, n, config, float(us)))
 
 
 def tune_save(path: str) -> None:
