@@ -167,15 +167,28 @@ typedef struct fb_plan fb_plan;
  * valid while the plan is launched.  Distinct descriptors must not share y. */
 fb_status fb_gemv_batched_plan(const fb_gemv_desc *descs, int32_t count, fb_plan **out);
 
+/* Autotunes the plan: descriptors are grouped by (format, log2 m, log2 n);
+ * for each group every tile compiled into the persistent kernel is timed on
+ * up to 16 of the group's own GEMVs (their y are overwritten), the fastest is
+ * stored in the tile cache and assigned to the whole group, and the device
+ * tables are rebuilt.  Synchronises `stream`. */
+fb_status fb_gemv_batched_tune(fb_plan *plan, int32_t reps, hipStream_t stream);
+
 /* Runs every GEMV of the plan in ONE persistent kernel: workgroups take
  * (descriptor, row tile) work items from a device counter until none remain.
- * The first launch on a stream captures a HIP graph (counter reset + kernel);
- * later launches on that stream replay it.  Each y equals fb_gemv_config on
- * the same descriptor with the plan's configuration, bit for bit. */
+ * The first launch builds and instantiates a HIP graph of two kernel nodes
+ * (counter reset, persistent kernel); later launches replay it, on any
+ * stream.  Launches of one plan must not overlap.  Each y equals
+ * fb_gemv_config on the same descriptor with the plan's configuration
+ * (fb_plan_config), bit for bit. */
 fb_status fb_gemv_batched_launch(fb_plan *plan, hipStream_t stream);
 
-/* Reference schedule: one fb_gemv_config launch per descriptor, in order. */
+/* Reference schedules: one fb_gemv_config launch per descriptor, in order,
+ * either issued from the host (loop) or as a prebuilt HIP graph with one
+ * kernel node per descriptor, chained in order (loop_graph, built on its first
+ * call).  Same results as fb_gemv_batched_launch. */
 fb_status fb_gemv_batched_loop(fb_plan *plan, hipStream_t stream);
+fb_status fb_gemv_batched_loop_graph(fb_plan *plan, hipStream_t stream);
 
 /* Algorithmic bytes of the plan (sum of m*n*k + native bytes of x and y). */
 int64_t fb_plan_bytes(const fb_plan *plan);

@@ -39,6 +39,26 @@ static fb_status launch_gemv(const GemvArgs& a, int tile, hipStream_t stream)
     return set_error(FB_ERR_ARG, "fb_gemv: bad tile configuration %d", tile);
 }
 
+// Kernel entry point and grid size of one GEMV launch with a given tile (used
+// to build graphs of GEMV launches).
+const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks)
+{
+    return dispatch_format(f, [&](auto tag) -> const void* {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        switch (tile) {
+#define FLYTE_TILE_FN(ID, LPR, RPW, U)                                                     \
+    case ID: {                                                                             \
+        using TL = GemvTile<LPR, RPW, U>;                                                  \
+        *blocks = (unsigned)((m + TL::rows_per_block - 1) / TL::rows_per_block);           \
+        return reinterpret_cast<const void*>(k_gemv<F, TL>);                               \
+    }
+            FLYTE_GEMV_TILES(FLYTE_TILE_FN)
+#undef FLYTE_TILE_FN
+        }
+        return nullptr;
+    });
+}
+
 fb_status gemv_validate(const char* what, fb_format f, int64_t m, int64_t n, const void* A, int64_t lda,
                         const void* x, const void* y)
 {
@@ -72,7 +92,7 @@ struct TuneKey {
     }
 };
 
-static int bucket(int64_t v)
+int tune_bucket(int64_t v)
 {
     int b = 0;
     while (v > 1) {
@@ -88,8 +108,14 @@ static std::map<TuneKey, std::pair<int, double>> g_tune;   // tile, microseconds
 int tune_lookup(fb_format f, int64_t m, int64_t n)
 {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(TuneKey{f.base, f.k, bucket(m), bucket(n)});
+    auto it = g_tune.find(TuneKey{f.base, f.k, tune_bucket(m), tune_bucket(n)});
     return it == g_tune.end() ? -1 : it->second.first;
+}
+
+void tune_store(fb_format f, int64_t m, int64_t n, int tile, double us)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[TuneKey{f.base, f.k, tune_bucket(m), tune_bucket(n)}] = {tile, us};
 }
 
 int gemv_pick_tile(fb_format f, int64_t m, int64_t n)
@@ -176,7 +202,7 @@ extern "C" fb_status fb_tune_gemv(fb_format f, int64_t m, int64_t n, const void*
     if (result != FB_OK) return result;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[TuneKey{f.base, f.k, bucket(m), bucket(n)}] = {best_tile, best_us};
+        g_tune[TuneKey{f.base, f.k, tune_bucket(m), tune_bucket(n)}] = {best_tile, best_us};
     }
     if (best) *best = best_tile;
     return FB_OK;
@@ -188,7 +214,7 @@ extern "C" fb_status fb_tune_record(fb_format f, int64_t m, int64_t n, int32_t c
     if (m <= 0 || n <= 0) return set_error(FB_ERR_ARG, "fb_tune_record: empty shape");
     if (config < 0 || config >= kGemvNumTiles) return set_error(FB_ERR_ARG, "fb_tune_record: bad config %d", config);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[TuneKey{f.base, f.k, bucket(m), bucket(n)}] = {config, us};
+    g_tune[TuneKey{f.base, f.k, tune_bucket(m), tune_bucket(n)}] = {config, us};
     return FB_OK;
 }
 

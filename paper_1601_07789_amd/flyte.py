@@ -59,8 +59,10 @@ _SIGS = {
     "fb_tune_load": (_I32, [ctypes.c_char_p]),
     "fb_tune_clear": (None, []),
     "fb_gemv_batched_plan": (_I32, [ctypes.POINTER(fb_gemv_desc), _I32, ctypes.POINTER(_P)]),
+    "fb_gemv_batched_tune": (_I32, [_P, _I32, _P]),
     "fb_gemv_batched_launch": (_I32, [_P, _P]),
     "fb_gemv_batched_loop": (_I32, [_P, _P]),
+    "fb_gemv_batched_loop_graph": (_I32, [_P, _P]),
     "fb_plan_bytes": (_I64, [_P]),
     "fb_plan_config": (_I32, [_P, _I32]),
     "fb_plan_destroy": (None, [_P]),
@@ -242,11 +244,17 @@ class BatchedGemv:
         _check(load().fb_gemv_batched_plan(arr, len(items), ctypes.byref(plan)))
         self._plan = plan
 
+    def tune(self, reps: int = 10, stream=None) -> None:
+        _check(load().fb_gemv_batched_tune(self._plan, reps, _stream(stream)))
+
     def launch(self, stream=None) -> None:
         _check(load().fb_gemv_batched_launch(self._plan, _stream(stream)))
 
     def loop(self, stream=None) -> None:
         _check(load().fb_gemv_batched_loop(self._plan, _stream(stream)))
+
+    def loop_graph(self, stream=None) -> None:
+        _check(load().fb_gemv_batched_loop_graph(self._plan, _stream(stream)))
 
     @property
     def nbytes(self) -> int:
