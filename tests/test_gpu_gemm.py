@@ -1,0 +1,171 @@
+"""GPU parity of fb_gemm against the exact oracle.
+
+Error measures (componentwise-normwise, so near-zero entries do not blow up):
+  e1 = max_ij |C_ij - C*_ij| / (|A||B|)_ij
+Bounds (K inner dimension, u32 = 2^-24, u64 = 2^-53, gamma_n(u) = n u / (1 - n u)):
+  BF16 ({32,2}):      products exact in FP32        -> e1 <= gamma_K(u32)
+  3-product ({32,3}): |lo| < 2^-7 |x|, lo*lo dropped -> e1 <= 2^-14 + gamma_3K(u32) (1 + 2^-7)^2
+  FP64 ({64,5|6}):    |unpack(C) - C*| <= gamma_K(u64) (|A||B|) + 2^-(m+1) (|C*| + gamma_K(u64) (|A||B|))
+Integer-valued FP64 data is exact in FP64, so its packed C must equal the
+oracle's pack of the exact product bit for bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import device, log
+from paper_1601_07789_amd import flyte, workloads
+
+pytestmark = pytest.mark.gpu
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+
+
+def gam(n, u):
+    return n * u / (1 - n * u)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.default()
+
+
+def all_entries(M, N):
+    ii, jj = np.meshgrid(np.arange(M), np.arange(N), indexing="ij")
+    return ii.reshape(-1), jj.reshape(-1)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_gemm_binary32_small_all_entries(dev, orc, k):
+    import torch
+    log(f"gemm b32 k={k} small")
+    M, N, K = 256, 384, 320
+    g = np.random.default_rng(11 + k)
+    Av = g.standard_normal((M, K)).astype(np.float32)
+    Bv = g.standard_normal((K, N)).astype(np.float32)
+    # a few rows/columns spanning a wide exponent range
+    Av[3] *= np.float32(2.0 ** 20)
+    Bv[:, 5] *= np.float32(2.0 ** -20)
+    A, B = orc.pack(32, k, Av.reshape(-1)), orc.pack(32, k, Bv.reshape(-1))
+    C = flyte.gemm((32, k), (32, k), (32, 4), M, N, K, torch.from_numpy(A).to(dev),
+                   torch.from_numpy(B).to(dev)).cpu().numpy().reshape(M, N).astype(np.float64)
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((32, k), (32, k), K, A, K, B, N, ii, jj)
+    e1 = np.max(np.abs(C.reshape(-1) - ce) / cab)
+    bound = gam(K, U32) if k == 2 else 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2
+    assert e1 <= bound, (e1, bound)
+    if k == 3:
+        # the 3-product must be far more accurate than plain BF16 of the rounded inputs
+        assert e1 < 2.0 ** -12
+
+
+def test_gemm_f64_integer_data_bit_exact(dev, orc):
+    import torch
+    log("gemm f64 integer")
+    M, N, K = 256, 256, 192
+    g = np.random.default_rng(5)
+    Av = g.integers(-64, 65, (M, K)).astype(np.float64)
+    Bv = g.integers(-64, 65, (K, N)).astype(np.float64)
+    exact = Av @ Bv                        # exact: |C| < 2^20
+    for kin in (5, 6):
+        A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
+        Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+        for kout in (2, 3, 4, 5, 6, 7, 8):
+            C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, Ad, Bd).cpu().numpy()
+            want = orc.pack(64, kout, exact.reshape(-1))
+            assert np.array_equal(C if kout < 8 else C.view(np.uint8), want), (kin, kout)
+
+
+@pytest.mark.parametrize("kin,kout", [(5, 5), (6, 6), (5, 8), (6, 3)])
+def test_gemm_f64_random_all_entries(dev, orc, kin, kout):
+    import torch
+    log(f"gemm f64 {kin}->{kout}")
+    M, N, K = 128, 256, 208
+    g = np.random.default_rng(7 + kin + kout)
+    Av = g.standard_normal((M, K)) * np.exp2(g.uniform(-30, 30, (M, 1)))
+    Bv = g.standard_normal((K, N))
+    A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
+    C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
+    Cu = orc.unpack(64, kout, C.cpu().numpy().view(np.uint8)) if kout < 8 else C.cpu().numpy()
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((64, kin), (64, kin), K, A, K, B, N, ii, jj)
+    m = 8 * kout - 12
+    bound = gam(K, U64) * cab + 2.0 ** -(m + 1) * (np.abs(ce) + gam(K, U64) * cab)
+    err = np.abs(Cu.reshape(-1) - ce)
+    assert np.all(err <= bound * (1 + 1e-12)), np.max(err / np.maximum(bound, 1e-300))
+
+
+def test_gemm_k_zero_gives_zero(dev):
+    import torch
+    A = torch.zeros(16, dtype=torch.uint8, device=dev)
+    B = torch.zeros(128 * 5, dtype=torch.uint8, device=dev)
+    C = torch.full((128 * 128 * 5,), 0x77, dtype=torch.uint8, device=dev)
+    flyte.gemm((64, 5), (64, 5), (64, 5), 128, 128, 0, A, B, C=C, lda=4, ldb=128)
+    assert torch.all(C == 0).item()
+
+
+def sampled(orc, fa, K, A, B, N, C, M, seed, count=256):
+    rng = np.random.default_rng(seed)
+    ii = np.concatenate([[0, M - 1], rng.integers(0, M, count)])
+    jj = np.concatenate([[0, N - 1], rng.integers(0, N, count)])
+    ce, cab = orc.gemm_entries(fa, fa, K, A, K, B, N, ii, jj)
+    return ii, jj, ce, cab
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_gemm_binary32_benchmark_size_sampled(dev, orc, k):
+    """M = N = K = 8192, N(0,1) entries (the precision-GEMM workload): sampled entries."""
+    import torch
+    log(f"gemm b32 k={k} 8192^3 sampled")
+    n = 8192
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 2)
+    v = torch.empty(n * n, dtype=torch.float32, device=dev).normal_(generator=g)
+    A = flyte.pack((32, k), v)
+    v.normal_(generator=g)
+    B = flyte.pack((32, k), v)
+    del v
+    C = flyte.gemm((32, k), (32, k), (32, 4), n, n, n, A, B)
+    torch.cuda.synchronize()
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    ii, jj, ce, cab = sampled(orc, (32, k), n, Ah, Bh, n, None, n, 3)
+    got = C.view(n, n)[torch.from_numpy(ii).to(dev), torch.from_numpy(jj).to(dev)].cpu().numpy().astype(np.float64)
+    e1 = np.max(np.abs(got - ce) / cab)
+    bound = gam(n, U32) if k == 2 else 2.0 ** -14 + gam(3 * n, U32) * (1 + 2.0 ** -7) ** 2
+    log(f"  e1 = {e1:.3e} (bound {bound:.3e})")
+    assert e1 <= bound
+    del A, B, C
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("k", [5, 6])
+def test_gemm_f64_benchmark_size_sampled(dev, orc, k):
+    """M = N = K = 16384, N(0,1) entries, C packed to the same k: sampled entries."""
+    import torch
+    log(f"gemm f64 k={k} 16384^3 sampled")
+    n = 16384
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 4)
+    v = torch.empty(n * n, dtype=torch.float64, device=dev).normal_(generator=g)
+    A = flyte.pack((64, k), v)
+    v.normal_(generator=g)
+    B = flyte.pack((64, k), v)
+    del v
+    C = flyte.gemm((64, k), (64, k), (64, k), n, n, n, A, B)
+    torch.cuda.synchronize()
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    ii, jj, ce, cab = sampled(orc, (64, k), n, Ah, Bh, n, None, n, 4, count=128)
+    idx = torch.from_numpy(((ii * n + jj)[:, None] * k + np.arange(k)[None, :]).reshape(-1)).to(dev)
+    got = orc.unpack(64, k, C[idx].cpu().numpy())
+    m = 8 * k - 12
+    bound = gam(n, U64) * cab + 2.0 ** -(m + 1) * (np.abs(ce) + gam(n, U64) * cab)
+    assert np.all(np.abs(got - ce) <= bound * (1 + 1e-12))
+    del A, B, C
+    torch.cuda.empty_cache()
