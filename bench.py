@@ -184,9 +184,13 @@ def main() -> int:
                           "achieved = sum of algorithmic bytes / sum of mean launch durations)"}
     del A64
 
+    # ------------------------------------------------------------ measured stream references
+    stream_ref = measure_streams(torch, dev, stream)
+
     # ------------------------------------------------------------ GEMM (after the timed region)
     detail = {"per_k": per_k, "vendor_fp64_gemv_us": round(vendor_us, 2), "rotate": R,
-              "bytes_per_step": bytes_per_step}
+              "bytes_per_step": bytes_per_step, "stream_reference": stream_ref,
+              "gemv_frac_of_measured_read_stream": round(achieved / stream_ref["read_GBps"], 4)}
     if not args.no_gemm:
         try:
             detail["gemm"] = bench_gemm(flyte, workloads, torch, np, dev, stream)
@@ -212,6 +216,29 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def measure_streams(torch, dev, stream):
+    """Plain read and copy bandwidth of the device (vendor kernels: torch.sum and
+    copy_ over 4 GiB), as a measured reference next to the nominal 8 TB/s."""
+    n = (4 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in [("read_GBps", lambda: a.sum(), 8 * n),
+                             ("copy_GBps", lambda: b.copy_(a), 16 * n)]:
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        out[name] = round(nbytes / (e0.elapsed_time(e1) / 5 * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(A, x, np):
