@@ -14,7 +14,7 @@ roofline entry reports the GEMV kernels' algorithmic bandwidth against the
 8 TB/s HBM peak.  GEMM throughput (BF16, 3-product, FP64 with a k-byte C) is
 measured after the timed region and reported under "detail".
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-gemm]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-gemm] [--retune]
 """
 from __future__ import annotations
 
@@ -29,6 +29,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "k-byte GEMV eff. GB/s (% HBM peak), speedup vs FP64-stored; GEMM TFLOP/s @tol"
+DEFAULT_TILES = os.path.join(ROOT, "paper_1601_07789_amd", "tuned", "gemv_mi355x.json")
+COUNTERS = os.path.join(ROOT, "profiles", "gemv_8192x8192_k3-8_hbm_counters.md")
 HBM_PEAK_GBPS = 8000.0
 M = N = 8192
 KS = [3, 4, 5, 6, 7, 8]
@@ -51,8 +53,10 @@ def main() -> int:
     ap.add_argument("--rotate", type=int, default=0, help="A copies per k (0: enough for >= 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
-    ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--tune-cache", default="", help="load tiles from this JSON if it exists, else tune and save")
+    ap.add_argument("--retune", action="store_true",
+                    help="tune the GEMV tiles with rotating buffers instead of loading the committed cache")
+    ap.add_argument("--tune-cache", default=DEFAULT_TILES,
+                    help="tile cache to load (default: the committed MI355X cache); with --retune, where to save")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -90,11 +94,10 @@ def main() -> int:
 
     # ------------------------------------------------------------ tile choice (rotating buffers)
     tiles = {}
-    if args.tune_cache and os.path.exists(args.tune_cache):
+    if not args.retune and os.path.exists(args.tune_cache):
         flyte.tune_load(args.tune_cache)
-        args.no_tune = True
         log(f"tiles loaded from {args.tune_cache}")
-    if not args.no_tune:
+    if args.retune:
         log("tuning GEMV tiles with rotating buffers")
         for k in KS:
             best = None
@@ -115,7 +118,7 @@ def main() -> int:
             tiles[k] = best[0]
     for k in KS:
         tiles.setdefault(k, flyte.tune_lookup((64, k), M, N))
-    if args.tune_cache and not os.path.exists(args.tune_cache):
+    if args.retune and args.tune_cache != DEFAULT_TILES:
         flyte.tune_save(args.tune_cache)
 
     # ------------------------------------------------------------ timed GEMV sweep
@@ -178,8 +181,9 @@ def main() -> int:
     tot_bytes = sum(gemv_bytes(k) for k in KS)
     tot_us = sum(per_k[k]["us"] for k in KS)
     achieved = tot_bytes / (tot_us * 1e-6) / 1e9
+    traffic = measured_traffic(tiles)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "flyte::k_gemv (binary64-derived k=3..8, one launch per k; "
                           "achieved = sum of algorithmic bytes / sum of mean launch durations)"}
     del A64
@@ -216,6 +220,35 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ["codec.hpp", "gemv_impl.hpp", "gemv.hip"]:
+        with open(os.path.join(ROOT, "paper_1601_07789_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(tiles):
+    """HBM bytes of one GEMV launch per k, summed over k (the unit of 'achieved'),
+    from the committed rocprofv3 counter summary -- or None if the kernel sources
+    or the tiles in use differ from those the counters were taken with."""
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    if f"source-sha256: {source_hash()}" not in text:
+        return None
+    rows = {}
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 4 and parts[0] == "traffic":
+            rows[int(parts[1])] = (int(parts[2]), int(parts[3]))
+    if any(k not in rows or rows[k][0] != tiles[k] for k in KS):
+        return None
+    return sum(rows[k][1] for k in KS)
 
 
 def measure_streams(torch, dev, stream):

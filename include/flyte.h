@@ -113,9 +113,10 @@ fb_status fb_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
 fb_status fb_gemv_config(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
                          const void *x, void *y, int32_t config, hipStream_t stream);
 
-/* Number of GEMV tile configurations, and a description of one
- * (rows per wave, waves per block, chunks in flight per lane; returns 0 if
- * config is out of range). */
+/* Number of GEMV tile configurations, and a description of one: returns the
+ * lanes that share a row group (0 if config is out of range) and writes the
+ * rows per wave, the waves that sweep the same rows together, and the units
+ * each lane loads per loop trip. */
 int32_t fb_gemv_num_configs(void);
 int32_t fb_gemv_config_info(int32_t config, int32_t *rows_per_wave, int32_t *waves_per_block,
                             int32_t *chunks_per_lane);

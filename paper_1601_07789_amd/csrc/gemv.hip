@@ -26,9 +26,9 @@ template <class F>
 static fb_status launch_gemv(const GemvArgs& a, int tile, hipStream_t stream)
 {
     switch (tile) {
-#define FLYTE_TILE_LAUNCH(ID, LPR, RPW, U)                                                   \
+#define FLYTE_TILE_LAUNCH(ID, LPR, RPW, U, KS, NT, ST)                                       \
     case ID: {                                                                               \
-        using TL = GemvTile<LPR, RPW, U>;                                                    \
+        using TL = GemvTile<LPR, RPW, U, KS, NT, ST>;                                        \
         const int64_t blocks = (a.m + TL::rows_per_block - 1) / TL::rows_per_block;          \
         k_gemv<F, TL><<<(unsigned)blocks, kGemvBlock, 0, stream>>>(a);                       \
         return check_launch("fb_gemv");                                                      \
@@ -46,9 +46,9 @@ const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks)
     return dispatch_format(f, [&](auto tag) -> const void* {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         switch (tile) {
-#define FLYTE_TILE_FN(ID, LPR, RPW, U)                                                     \
+#define FLYTE_TILE_FN(ID, LPR, RPW, U, KS, NT, ST)                                         \
     case ID: {                                                                             \
-        using TL = GemvTile<LPR, RPW, U>;                                                  \
+        using TL = GemvTile<LPR, RPW, U, KS, NT, ST>;                                      \
         *blocks = (unsigned)((m + TL::rows_per_block - 1) / TL::rows_per_block);           \
         return reinterpret_cast<const void*>(k_gemv<F, TL>);                               \
     }
@@ -136,7 +136,7 @@ extern "C" int32_t fb_gemv_config_info(int32_t config, int32_t* rows_per_wave, i
     if (config < 0 || config >= kGemvNumTiles) return 0;
     const TileInfo t = gemv_tile_info(config);
     if (rows_per_wave) *rows_per_wave = (64 / t.lpr) * t.rpw;
-    if (waves_per_block) *waves_per_block = kGemvWaves;
+    if (waves_per_block) *waves_per_block = t.ks;
     if (chunks_per_lane) *chunks_per_lane = t.u;
     return t.lpr;
 }

@@ -188,7 +188,7 @@ def gemv_num_configs() -> int:
 def gemv_config_info(config: int):
     rpw, wpb, cpl = _I32(), _I32(), _I32()
     lpr = load().fb_gemv_config_info(config, ctypes.byref(rpw), ctypes.byref(wpb), ctypes.byref(cpl))
-    return {"lanes_per_row": lpr, "rows_per_wave": rpw.value, "waves_per_block": wpb.value,
+    return {"lanes_per_row": lpr, "rows_per_wave": rpw.value, "waves_per_row_group": wpb.value,
             "units_per_lane": cpl.value}
 
 
