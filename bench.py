@@ -53,6 +53,7 @@ def main() -> int:
     ap.add_argument("--rotate", type=int, default=0, help="A copies per k (0: enough for >= 1 GiB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--retune", action="store_true",
                     help="tune the GEMV tiles with rotating buffers instead of loading the committed cache")
     ap.add_argument("--tune-cache", default=DEFAULT_TILES,
@@ -191,20 +192,27 @@ def main() -> int:
     # ------------------------------------------------------------ measured stream references
     stream_ref = measure_streams(torch, dev, stream)
 
+    # ------------------------------------------------------------ CPU baseline: the oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(A, x, np)
+
     # ------------------------------------------------------------ GEMM (after the timed region)
     detail = {"per_k": per_k, "vendor_fp64_gemv_us": round(vendor_us, 2), "rotate": R,
               "bytes_per_step": bytes_per_step, "stream_reference": stream_ref,
               "gemv_frac_of_measured_read_stream": round(achieved / stream_ref["read_GBps"], 4)}
+    del A
+    torch.cuda.empty_cache()
     if not args.no_gemm:
         try:
             detail["gemm"] = bench_gemm(flyte, workloads, torch, np, dev, stream)
         except Exception as e:   # reported, not hidden: the GEMV line stands on its own
             detail["gemm"] = {"error": f"{type(e).__name__}: {e}"}
-
-    # ------------------------------------------------------------ CPU baseline: the oracle
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(A, x, np)
+    if not args.no_batched:
+        try:
+            detail["batched"] = bench_batched(flyte, workloads, torch, dev, stream)
+        except Exception as e:
+            detail["batched"] = {"error": f"{type(e).__name__}: {e}"}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -297,6 +305,56 @@ def cpu_baseline(A, x, np):
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle fbo_gemv_naive (one thread), full 8192x8192 GEMV per k = 3..8, "
                       f"passes per k = {passes}; {total_s:.1f} s of CPU time"}
+
+
+def bench_batched(flyte, workloads, torch, dev, stream):
+    """4096 independent GEMVs, m and n log-uniform in [64, 4096], formats uniform over
+    all ten, entries U(-1,1): one persistent graph-launched kernel against the host
+    loop of per-call launches and against that loop as a prebuilt graph."""
+    descs = workloads.batched_descs(4096, workloads.SEED_BASE + 3)
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 3)
+    pool = {32: torch.empty(4096 * 4096, dtype=torch.float32, device=dev).uniform_(-1, 1, generator=g),
+            64: torch.empty(4096 * 4096, dtype=torch.float64, device=dev).uniform_(-1, 1, generator=g)}
+    items = []
+    for d in descs:
+        f = (d["base"], d["k"])
+        src = pool[d["base"]][: d["m"] * d["lda"]]
+        A = flyte.pack(f, src)
+        x = pool[d["base"]][1000: 1000 + d["n"]].clone()
+        y = torch.empty(d["m"], dtype=src.dtype, device=dev)
+        items.append(flyte.GemvItem(f, d["m"], d["n"], d["lda"], A, x, y))
+    del pool
+    plan = flyte.BatchedGemv(items)
+    t0 = time.perf_counter()
+    plan.tune(reps=3)
+    tune_s = time.perf_counter() - t0
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_persistent = timed(plan.launch, 5)
+    ms_loop = timed(plan.loop, 3)
+    ms_loop_graph = timed(plan.loop_graph, 3)
+    nbytes = plan.nbytes
+    out = {"count": len(items), "bytes": nbytes, "tune_s": round(tune_s, 2),
+           "persistent_graph_ms": round(ms_persistent, 3),
+           "persistent_graph_GBps": round(nbytes / (ms_persistent * 1e-3) / 1e9, 1),
+           "loop_ms": round(ms_loop, 3), "loop_graph_ms": round(ms_loop_graph, 3),
+           "speedup_vs_loop": round(ms_loop / ms_persistent, 3),
+           "speedup_vs_loop_graph": round(ms_loop_graph / ms_persistent, 3)}
+    plan.close()
+    del items
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_gemm(flyte, workloads, torch, np, dev, stream):
