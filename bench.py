@@ -54,6 +54,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-blas1", action="store_true")
     ap.add_argument("--retune", action="store_true",
                     help="tune the GEMV tiles with rotating buffers instead of loading the committed cache")
     ap.add_argument("--tune-cache", default=DEFAULT_TILES,
@@ -208,6 +209,11 @@ def main() -> int:
             detail["gemm"] = bench_gemm(flyte, workloads, torch, np, dev, stream)
         except Exception as e:   # reported, not hidden: the GEMV line stands on its own
             detail["gemm"] = {"error": f"{type(e).__name__}: {e}"}
+    if not args.no_blas1:
+        try:
+            detail["blas1"] = bench_blas1(flyte, workloads, torch, dev, stream)
+        except Exception as e:
+            detail["blas1"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_batched:
         try:
             detail["batched"] = bench_batched(flyte, workloads, torch, dev, stream)
@@ -305,6 +311,58 @@ def cpu_baseline(A, x, np):
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle fbo_gemv_naive (one thread), full 8192x8192 GEMV per k = 3..8, "
                       f"passes per k = {passes}; {total_s:.1f} s of CPU time"}
+
+
+def bench_blas1(flyte, workloads, torch, dev, stream):
+    """Streaming codec and BLAS-1 kernels on n = 2^28 elements (the 2 GiB FP64 side
+    and every packed array exceed the 256 MB last-level cache): algorithmic GB/s and
+    fraction of 8 TB/s.  pack: n(W+k) bytes, unpack: n(k+W), axpy: 3nk, dot: 2nk."""
+    n = 1 << 28
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 1)
+    nat = torch.empty(n, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=g)
+    out = {"n": n}
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    def rate(nbytes, sec):
+        gbs = nbytes / sec / 1e9
+        return {"GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBPS, 4)}
+
+    back = torch.empty_like(nat)
+    res = {"pack": {}, "unpack": {}, "axpy": {}, "dot": {}}
+    for k in range(2, 9):
+        x = flyte.pack((64, k), nat)
+        res["pack"][k] = rate(n * (8 + k), timed(lambda: flyte.pack((64, k), nat, out=x)))
+        res["unpack"][k] = rate(n * (k + 8), timed(lambda: flyte.unpack((64, k), x, out=back)))
+        if k >= 3:
+            y = x.clone()
+            res["axpy"][k] = rate(3 * n * k, timed(lambda: flyte.axpy((64, k), 1.0 / 3.0, x, y)))
+            r = torch.empty((), dtype=torch.float64, device=dev)
+            res["dot"][k] = rate(2 * n * k, timed(lambda: flyte.dot((64, k), x, y, out=r)))
+            del y
+        del x
+    del nat, back
+    nat32 = torch.empty(n, dtype=torch.float32, device=dev).uniform_(-1.0, 1.0, generator=g)
+    back32 = torch.empty_like(nat32)
+    for k in (2, 3):
+        x = flyte.pack((32, k), nat32)
+        res["pack"][f"b32k{k}"] = rate(n * (4 + k), timed(lambda: flyte.pack((32, k), nat32, out=x)))
+        res["unpack"][f"b32k{k}"] = rate(n * (k + 4), timed(lambda: flyte.unpack((32, k), x, out=back32)))
+        del x
+    del nat32, back32
+    torch.cuda.empty_cache()
+    out.update(res)
+    return out
 
 
 def bench_batched(flyte, workloads, torch, dev, stream):
