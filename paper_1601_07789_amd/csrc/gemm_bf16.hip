@@ -247,17 +247,19 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
         }
     };
 
+    // the last K step is peeled so the loop body has no branches
     const int KT = K / GB_BK;
     load_tiles(0);
     store_tiles(0);
     __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
+    for (int kt = 0; kt < KT - 1; ++kt) {
         const int s = kt & 1;
-        if (kt + 1 < KT) load_tiles((kt + 1) * GB_BK);
+        load_tiles((kt + 1) * GB_BK);
         compute(s);
-        if (kt + 1 < KT) store_tiles(s ^ 1);
+        store_tiles(s ^ 1);
         __syncthreads();
     }
+    compute((KT - 1) & 1);
 
     // ---- epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 tile
 #pragma unroll

@@ -53,7 +53,7 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
 }
 
 template <int KIN, int KOUT>
-__global__ void __launch_bounds__(GD_THREADS)
+__global__ void __launch_bounds__(GD_THREADS, 2)
 k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K)
 {
@@ -133,17 +133,19 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         }
     };
 
+    // the last K step is peeled so the loop body has no branches
     const int KT = K / GD_BK;
     load_tiles(0);
     store_tiles(0);
     __syncthreads();
-    for (int kt = 0; kt < KT; ++kt) {
+    for (int kt = 0; kt < KT - 1; ++kt) {
         const int s = kt & 1;
-        if (kt + 1 < KT) load_tiles((kt + 1) * GD_BK);
+        load_tiles((kt + 1) * GD_BK);
         compute(s);
-        if (kt + 1 < KT) store_tiles(s ^ 1);
+        store_tiles(s ^ 1);
         __syncthreads();
     }
+    compute((KT - 1) & 1);
 
     // ---- epilogue: round to the output format and store whole dword groups
     constexpr int GO = FO::G;
