@@ -10,13 +10,18 @@
 //    product is hi*hi + hi*lo + lo*hi: three BF16 MFMAs per step into the same
 //    FP32 accumulators (lo*lo, below 2^-16 relative, is dropped).
 //
-// Tiling: a 256-thread workgroup computes a 128 x 128 tile of C; each of its
-// 4 waves a 64 x 64 quarter as 4 x 4 v_mfma_f32_16x16x32_bf16 tiles.  K is
-// walked in steps of 64 through double-buffered LDS (one barrier per step;
-// the next step's global loads are issued before the current step's MFMAs).
-// LDS rows are padded to 144 bytes, so the 16-byte operand reads of 16 lanes
-// hit distinct banks.  B is stored in LDS transposed (n-major, k contiguous):
-// each thread loads 8 rows of B and transposes them in registers with
+// Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
+// wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
+// wave tiles keep LDS operand traffic below the LDS bandwidth: BF16 uses
+// 256 x 256 x 64 tiles with 8 waves of 128 x 64 (about 94 B/clk of LDS reads
+// per CU at the MFMA peak, against 128 available); the 3-product uses
+// 256 x 128 x 32 with 4 waves of 128 x 64 (three MFMAs per operand pair);
+// shapes that are not multiples of those use 128 x 128 x 64.  K is walked in
+// BK steps through double-buffered LDS (one barrier per step; the next step's
+// global loads are issued before the current step's MFMAs; the last step is
+// peeled).  LDS rows are padded by 16 bytes, so the 16-byte operand reads of
+// 16 lanes hit distinct banks.  B is stored in LDS transposed (n-major, k contiguous):
+// each thread loads KR rows of B and transposes them in registers with
 // v_perm_b32, so every MFMA operand is one ds_read_b128.  Workgroups are
 // renumbered so that consecutive tiles of C run on the same XCD (sharing its
 // L2), grouped 8 tile-rows at a time.
@@ -28,10 +33,6 @@ namespace flyte {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-
-constexpr int GB_BM = 128, GB_BN = 128, GB_BK = 64, GB_THREADS = 256;
-constexpr int GB_LDS_ROW = GB_BK + 8;                 // bf16 per padded LDS row (144 bytes)
-constexpr int GB_TILE = GB_BM * GB_LDS_ROW;           // bf16 per operand tile
 
 // Tile index of this workgroup: XCD-aware renumbering, then 8-row groups.
 __device__ __forceinline__ void gemm_tile_coords(int ntm, int ntn, int& tm, int& tn)
@@ -62,86 +63,99 @@ __device__ __forceinline__ void split_hi_lo(uint32_t u, uint32_t& hi, uint32_t& 
     lo = ((u & 0x7F800000u) == 0x7F800000u) ? 0u : bf16_rne(__float_as_uint(r));
 }
 
-template <int MODE>
-struct GemmStage {
-    static constexpr int PARTS = MODE ? 2 : 1;
+// Tile configuration: BM x BN x BK workgroup tile, WGM x WGN waves (wave tile
+// (BM/WGM) x (BN/WGN) as 16 x 16 MFMA tiles), B loaded in groups of KR rows.
+// Stores KR bf16 (KR/2 dwords) at an LDS address: one ds_write_b128 or b64.
+template <int KR>
+__device__ __forceinline__ void store_row_chunk(uint16_t* dst, const uint32_t (&v)[KR / 2])
+{
+    if constexpr (KR == 8) {
+        *reinterpret_cast<u32x4_t*>(dst) = u32x4_t{v[0], v[1], v[2], v[3]};
+    } else {
+        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+        *reinterpret_cast<u32x2_t*>(dst) = u32x2_t{v[0], v[1]};
+    }
+}
+
+template <int MODE, int BM, int BN, int BK, int WGM, int WGN, int KR>
+struct B32Tile {
+    static constexpr int THREADS = 64 * WGM * WGN;
+    static constexpr int TM = BM / WGM, TN = BN / WGN;
+    static constexpr int FM = TM / 16, FN = TN / 16;
+    static constexpr int PARTS = MODE ? 2 : 1;          // hi (and lo) operand tiles
+    static constexpr int KB = MODE ? 3 : 2;             // stored bytes per element
+    static constexpr int ROW = BK + 8;                  // bf16 per padded LDS row
+    static constexpr int A_TILE = BM * ROW, B_TILE = BN * ROW;
+    static constexpr int STAGE = PARTS * (A_TILE + B_TILE);
+    // A: chunks of A_EL consecutive elements of a row (16 or 48 bytes)
+    static constexpr int A_EL = MODE ? 16 : 8;
+    static constexpr int A_CPR = BK / A_EL;
+    static constexpr int A_N = BM * A_CPR / THREADS;
+    static constexpr int A_DW = A_EL * KB / 4;
+    // B: groups of KR k-rows x BCOL columns (one dword or one 4-element unit per row)
+    static constexpr int BCOL = MODE ? 4 : 2;
+    static constexpr int B_GPR = BN / BCOL;
+    static constexpr int B_G = (BK / KR) * B_GPR / THREADS;
+    static constexpr int B_DW = MODE ? 3 : 1;
+    static_assert(BK % 32 == 0 && TM % 16 == 0 && TN % 16 == 0, "tile shape");
+    static_assert(A_N * THREADS == BM * A_CPR && A_N >= 1, "A staging must divide evenly");
+    static_assert(B_G * THREADS == (BK / KR) * B_GPR && B_G >= 1, "B staging must divide evenly");
+    static_assert(KR == 4 || KR == 8, "B group rows");
 };
 
-template <int MODE>
-__global__ void __launch_bounds__(GB_THREADS)
-k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
-            float* __restrict__ C, int64_t ldc, int M, int N, int K)
+template <int MODE, int BM, int BN, int BK, int WGM, int WGN, int KR>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
+           float* __restrict__ C, int64_t ldc, int M, int N, int K)
 {
-    constexpr int PARTS = GemmStage<MODE>::PARTS;
-    constexpr int KB = MODE ? 3 : 2;   // stored bytes per element
-    // [stage][A parts..., B parts...][tile]
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2][2 * PARTS][GB_TILE];
+    using T = B32Tile<MODE, BM, BN, BK, WGM, WGN, KR>;
+    constexpr int THREADS = T::THREADS, PARTS = T::PARTS, KB = T::KB, ROW = T::ROW;
+    constexpr int FM = T::FM, FN = T::FN;
+    // [stage][A hi, (A lo), B hi, (B lo)]
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2][T::STAGE];
 
-    const int ntm = M / GB_BM, ntn = N / GB_BN;
+    const int ntm = M / BM, ntn = N / BN;
     int tm, tn;
     gemm_tile_coords(ntm, ntn, tm, tn);
-    const int m0 = tm * GB_BM, n0 = tn * GB_BN;
+    const int m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
-    const int wm = wid / 2, wn = wid % 2;
+    const int wm = wid / WGN, wn = wid % WGN;
 
-    // ---- global -> register staging
-    // A: MODE 0: 4 chunks of 8 elements (16 B) per thread; MODE 1: 2 units of 16 elements (48 B).
-    constexpr int A_N = MODE ? 2 : 4;
-    constexpr int A_DW = MODE ? 12 : 4;
-    uint32_t ra[A_N][A_DW];
-    // B: MODE 0: 2 groups of 8 rows x 2 columns (one dword per row); MODE 1: 1 group of 8 rows x 4 columns (3 dwords per row).
-    constexpr int B_G = MODE ? 1 : 2;
-    constexpr int B_DW = MODE ? 3 : 1;
-    uint32_t rb[B_G][8][B_DW];
+    uint32_t ra[T::A_N][T::A_DW];
+    uint32_t rb[T::B_G][KR][T::B_DW];
+
+    auto a_tile = [&](int s, int part) { return lds[s] + part * T::A_TILE; };
+    auto b_tile = [&](int s, int part) { return lds[s] + PARTS * T::A_TILE + part * T::B_TILE; };
 
     auto load_tiles = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < A_N; ++i) {
-            if constexpr (MODE == 0) {
-                const int c = t + GB_THREADS * i, row = c / 8, kc = c % 8;
-                const uint32_t* p = reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * 8) * KB);
-                load_dwords(p, ra[i]);
-            } else {
-                const int u = t + GB_THREADS * i, row = u / 4, uc = u % 4;
-                const uint32_t* p = reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + uc * 16) * KB);
-                load_dwords(p, ra[i]);
-            }
+        for (int i = 0; i < T::A_N; ++i) {
+            const int c = t + THREADS * i, row = c / T::A_CPR, kc = c % T::A_CPR;
+            load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * T::A_EL) * KB),
+                        ra[i]);
         }
 #pragma unroll
-        for (int g = 0; g < B_G; ++g) {
-            if constexpr (MODE == 0) {
-                const int np = t % 64, kg = t / 64 + 4 * g;
+        for (int g = 0; g < T::B_G; ++g) {
+            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const uint32_t* p = reinterpret_cast<const uint32_t*>(
-                        B + ((int64_t)(k0 + kg * 8 + r) * ldb + n0 + 2 * np) * KB);
-                    rb[g][r][0] = *p;
-                }
-            } else {
-                const int ng = t % 32, kg = t / 32;
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const uint32_t* p = reinterpret_cast<const uint32_t*>(
-                        B + ((int64_t)(k0 + kg * 8 + r) * ldb + n0 + 4 * ng) * KB);
-                    load_dwords(p, rb[g][r]);
-                }
-            }
+            for (int r = 0; r < KR; ++r)
+                load_dwords(reinterpret_cast<const uint32_t*>(
+                                B + ((int64_t)(k0 + kg * KR + r) * ldb + n0 + T::BCOL * np) * KB),
+                            rb[g][r]);
         }
     };
 
     auto store_tiles = [&](int s) {
-        uint16_t* As_hi = lds[s][0];
-        uint16_t* Bs_hi = lds[s][PARTS];
+        uint16_t* Ah = a_tile(s, 0);
+        uint16_t* Bh = b_tile(s, 0);
 #pragma unroll
-        for (int i = 0; i < A_N; ++i) {
+        for (int i = 0; i < T::A_N; ++i) {
+            const int c = t + THREADS * i, row = c / T::A_CPR, kc = c % T::A_CPR;
             if constexpr (MODE == 0) {
-                const int c = t + GB_THREADS * i, row = c / 8, kc = c % 8;
-                *reinterpret_cast<u32x4_t*>(As_hi + row * GB_LDS_ROW + kc * 8) =
-                    u32x4_t{ra[i][0], ra[i][1], ra[i][2], ra[i][3]};
+                *reinterpret_cast<u32x4_t*>(Ah + row * ROW + kc * 8) = u32x4_t{ra[i][0], ra[i][1], ra[i][2], ra[i][3]};
             } else {
                 using F = Fmt<32, 3>;
-                uint16_t* As_lo = lds[s][1];
-                const int u = t + GB_THREADS * i, row = u / 4, uc = u % 4;
+                uint16_t* Al = a_tile(s, 1);
                 uint32_t x[16];
                 unpack_elems<F, 16>(ra[i], x);
                 uint32_t hi[8], lo[8];
@@ -153,8 +167,8 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
                     hi[e / 2] = h0 | (h1 << 16);
                     lo[e / 2] = l0 | (l1 << 16);
                 }
-                u32x4_t* dh = reinterpret_cast<u32x4_t*>(As_hi + row * GB_LDS_ROW + uc * 16);
-                u32x4_t* dl = reinterpret_cast<u32x4_t*>(As_lo + row * GB_LDS_ROW + uc * 16);
+                u32x4_t* dh = reinterpret_cast<u32x4_t*>(Ah + row * ROW + kc * 16);
+                u32x4_t* dl = reinterpret_cast<u32x4_t*>(Al + row * ROW + kc * 16);
                 dh[0] = u32x4_t{hi[0], hi[1], hi[2], hi[3]};
                 dh[1] = u32x4_t{hi[4], hi[5], hi[6], hi[7]};
                 dl[0] = u32x4_t{lo[0], lo[1], lo[2], lo[3]};
@@ -162,25 +176,24 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
             }
         }
 #pragma unroll
-        for (int g = 0; g < B_G; ++g) {
+        for (int g = 0; g < T::B_G; ++g) {
+            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
             if constexpr (MODE == 0) {
-                const int np = t % 64, kg = t / 64 + 4 * g;
-                uint32_t c0[4], c1[4];
+                // row r holds columns (2np, 2np+1) as low/high halves: transpose to k-contiguous columns
+                uint32_t c0[KR / 2], c1[KR / 2];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    // low halves (column 2np) and high halves (column 2np+1) of rows 2i, 2i+1
+                for (int i = 0; i < KR / 2; ++i) {
                     c0[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1][0], rb[g][2 * i][0], 0x05040100u);
                     c1[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1][0], rb[g][2 * i][0], 0x07060302u);
                 }
-                *reinterpret_cast<u32x4_t*>(Bs_hi + (2 * np) * GB_LDS_ROW + kg * 8) = u32x4_t{c0[0], c0[1], c0[2], c0[3]};
-                *reinterpret_cast<u32x4_t*>(Bs_hi + (2 * np + 1) * GB_LDS_ROW + kg * 8) = u32x4_t{c1[0], c1[1], c1[2], c1[3]};
+                store_row_chunk<KR>(Bh + (2 * np) * ROW + kg * KR, c0);
+                store_row_chunk<KR>(Bh + (2 * np + 1) * ROW + kg * KR, c1);
             } else {
                 using F = Fmt<32, 3>;
-                uint16_t* Bs_lo = lds[s][3];
-                const int ng = t % 32, kg = t / 32;
-                uint32_t hi[8][4], lo[8][4];   // [row][column]
+                uint16_t* Bl = b_tile(s, 1);
+                uint32_t hi[KR][4], lo[KR][4];   // [row][column]
 #pragma unroll
-                for (int r = 0; r < 8; ++r) {
+                for (int r = 0; r < KR; ++r) {
                     uint32_t x[4];
                     unpack_elems<F, 4>(rb[g][r], x);
 #pragma unroll
@@ -188,57 +201,58 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
                 }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    u32x4_t vh, vl;
-                    vh.x = hi[0][c] | (hi[1][c] << 16); vh.y = hi[2][c] | (hi[3][c] << 16);
-                    vh.z = hi[4][c] | (hi[5][c] << 16); vh.w = hi[6][c] | (hi[7][c] << 16);
-                    vl.x = lo[0][c] | (lo[1][c] << 16); vl.y = lo[2][c] | (lo[3][c] << 16);
-                    vl.z = lo[4][c] | (lo[5][c] << 16); vl.w = lo[6][c] | (lo[7][c] << 16);
-                    *reinterpret_cast<u32x4_t*>(Bs_hi + (4 * ng + c) * GB_LDS_ROW + kg * 8) = vh;
-                    *reinterpret_cast<u32x4_t*>(Bs_lo + (4 * ng + c) * GB_LDS_ROW + kg * 8) = vl;
+                    uint32_t vh[KR / 2], vl[KR / 2];
+#pragma unroll
+                    for (int i = 0; i < KR / 2; ++i) {
+                        vh[i] = hi[2 * i][c] | (hi[2 * i + 1][c] << 16);
+                        vl[i] = lo[2 * i][c] | (lo[2 * i + 1][c] << 16);
+                    }
+                    store_row_chunk<KR>(Bh + (4 * np + c) * ROW + kg * KR, vh);
+                    store_row_chunk<KR>(Bl + (4 * np + c) * ROW + kg * KR, vl);
                 }
             }
         }
     };
 
-    f32x4_t acc[4][4];
+    f32x4_t acc[FM][FN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FN; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
     auto compute = [&](int s) {
-        const uint16_t* As_hi = lds[s][0];
-        const uint16_t* Bs_hi = lds[s][PARTS];
+        const uint16_t* Ah = a_tile(s, 0);
+        const uint16_t* Bh = b_tile(s, 0);
         const int r16 = lane % 16, kq = 8 * (lane / 16);
 #pragma unroll
-        for (int ks = 0; ks < GB_BK / 32; ++ks) {
-            bf16x8_t a[4], b[4];
+        for (int ks = 0; ks < BK / 32; ++ks) {
+            bf16x8_t a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                a[i] = *reinterpret_cast<const bf16x8_t*>(As_hi + (wm * 64 + i * 16 + r16) * GB_LDS_ROW + ks * 32 + kq);
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                b[j] = *reinterpret_cast<const bf16x8_t*>(Bs_hi + (wn * 64 + j * 16 + r16) * GB_LDS_ROW + ks * 32 + kq);
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
             if constexpr (MODE == 0) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
             } else {
-                const uint16_t* As_lo = lds[s][1];
-                const uint16_t* Bs_lo = lds[s][3];
-                bf16x8_t al[4], bl[4];
+                const uint16_t* Al = a_tile(s, 1);
+                const uint16_t* Bl = b_tile(s, 1);
+                bf16x8_t al[FM], bl[FN];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    al[i] = *reinterpret_cast<const bf16x8_t*>(As_lo + (wm * 64 + i * 16 + r16) * GB_LDS_ROW + ks * 32 + kq);
+                for (int i = 0; i < FM; ++i)
+                    al[i] = *reinterpret_cast<const bf16x8_t*>(Al + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bl[j] = *reinterpret_cast<const bf16x8_t*>(Bs_lo + (wn * 64 + j * 16 + r16) * GB_LDS_ROW + ks * 32 + kq);
+                for (int j = 0; j < FN; ++j)
+                    bl[j] = *reinterpret_cast<const bf16x8_t*>(Bl + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < FN; ++j) {
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
@@ -248,13 +262,13 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
     };
 
     // the last K step is peeled so the loop body has no branches
-    const int KT = K / GB_BK;
+    const int KT = K / BK;
     load_tiles(0);
     store_tiles(0);
     __syncthreads();
     for (int kt = 0; kt < KT - 1; ++kt) {
         const int s = kt & 1;
-        load_tiles((kt + 1) * GB_BK);
+        load_tiles((kt + 1) * BK);
         compute(s);
         store_tiles(s ^ 1);
         __syncthreads();
@@ -263,35 +277,46 @@ k_gemm_bf16(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restric
 
     // ---- epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each 16 x 16 tile
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 64 + i * 16 + 4 * (lane / 16) + r;
-                const int col = n0 + wn * 64 + j * 16 + lane % 16;
+                const int row = m0 + wm * T::TM + i * 16 + 4 * (lane / 16) + r;
+                const int col = n0 + wn * T::TN + j * 16 + lane % 16;
                 C[(int64_t)row * ldc + col] = acc[i][j][r];
             }
+}
+
+template <int MODE, int BM, int BN, int BK, int WGM, int WGN, int KR>
+static void launch_b32(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                       int64_t ldc, hipStream_t stream)
+{
+    const unsigned blocks = (unsigned)((M / BM) * (N / BN));
+    k_gemm_b32<MODE, BM, BN, BK, WGM, WGN, KR><<<blocks, 64 * WGM * WGN, 0, stream>>>(
+        static_cast<const uint8_t*>(A), lda, static_cast<const uint8_t*>(B), ldb, static_cast<float*>(C), ldc, (int)M,
+        (int)N, (int)K);
 }
 
 fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
                            int64_t ldb, void* C, int64_t ldc, hipStream_t stream)
 {
-    if (M % GB_BM || N % GB_BN || K % GB_BK)
-        return set_error(FB_ERR_UNSUPPORTED, "fb_gemm: binary32 paths need M, N multiples of %d and K of %d", GB_BM,
-                         GB_BK);
+    if (M % 128 || N % 128 || K % 64)
+        return set_error(FB_ERR_UNSUPPORTED, "fb_gemm: binary32 paths need M, N multiples of 128 and K of 64");
     if (M == 0 || N == 0) return FB_OK;
-    const int64_t blocks = (M / GB_BM) * (N / GB_BN);
-    if (blocks > INT32_MAX || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+    if ((M / 128) * (N / 128) > INT32_MAX || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
         return set_error(FB_ERR_ARG, "fb_gemm: sizes too large");
-    if (mode == 0)
-        k_gemm_bf16<0><<<(unsigned)blocks, GB_THREADS, 0, stream>>>(static_cast<const uint8_t*>(A), lda,
-                                                                     static_cast<const uint8_t*>(B), ldb,
-                                                                     static_cast<float*>(C), ldc, (int)M, (int)N, (int)K);
-    else
-        k_gemm_bf16<1><<<(unsigned)blocks, GB_THREADS, 0, stream>>>(static_cast<const uint8_t*>(A), lda,
-                                                                     static_cast<const uint8_t*>(B), ldb,
-                                                                     static_cast<float*>(C), ldc, (int)M, (int)N, (int)K);
+    if (mode == 0) {
+        if (M % 256 == 0 && N % 256 == 0)
+            launch_b32<0, 256, 256, 64, 2, 4, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        else
+            launch_b32<0, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    } else {
+        if (M % 256 == 0)
+            launch_b32<1, 256, 128, 32, 2, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        else
+            launch_b32<1, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    }
     return check_launch("fb_gemm");
 }
 

@@ -43,10 +43,12 @@ def all_entries(M, N):
 
 
 @pytest.mark.parametrize("k", [2, 3])
-def test_gemm_binary32_small_all_entries(dev, orc, k):
+@pytest.mark.parametrize("shape", [(256, 384, 320), (512, 512, 192), (128, 256, 64)])
+def test_gemm_binary32_small_all_entries(dev, orc, k, shape):
+    """Every entry; the shapes exercise the 256 x 256, 256 x 128 and 128 x 128 tile paths."""
     import torch
-    log(f"gemm b32 k={k} small")
-    M, N, K = 256, 384, 320
+    log(f"gemm b32 k={k} {shape}")
+    M, N, K = shape
     g = np.random.default_rng(11 + k)
     Av = g.standard_normal((M, K)).astype(np.float32)
     Bv = g.standard_normal((K, N)).astype(np.float32)
