@@ -169,10 +169,10 @@ typedef struct fb_plan fb_plan;
 fb_status fb_gemv_batched_plan(const fb_gemv_desc *descs, int32_t count, fb_plan **out);
 
 /* Autotunes the plan: descriptors are grouped by (format, log2 m, log2 n);
- * for each group every tile compiled into the persistent kernel is timed on
- * up to 16 of the group's own GEMVs (their y are overwritten), the fastest is
- * stored in the tile cache and assigned to the whole group, and the device
- * tables are rebuilt.  Synchronises `stream`. */
+ * for each group, up to 64 of its own GEMVs are run alone in the persistent
+ * kernel with every tile compiled into it (their y are overwritten), the
+ * fastest tile is stored in the tile cache and assigned to the whole group,
+ * and the device tables are rebuilt.  Synchronises `stream`. */
 fb_status fb_gemv_batched_tune(fb_plan *plan, int32_t reps, hipStream_t stream);
 
 /* Runs every GEMV of the plan in ONE persistent kernel: workgroups take

@@ -37,9 +37,11 @@ const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks);
 int tune_bucket(int64_t v);
 
 // Tiles compiled into the persistent kernel (public GEMV config ids); the
-// order is the slot order of run_format below.
-constexpr int kBatchedNumTiles = 6;
-static const int kBatchedTile[kBatchedNumTiles] = {2, 3, 5, 7, 9, 11};
+// order is the slot order of run_format below.  The set is kept light in
+// registers (the kernel's register budget is the largest of its paths) so
+// three workgroups fit per CU without spilling.
+constexpr int kBatchedNumTiles = 8;
+static const int kBatchedTile[kBatchedNumTiles] = {11, 12, 9, 10, 33, 32, 21, 7};
 
 static int batched_slot(int tile)
 {
@@ -66,21 +68,31 @@ struct WorkItem {
 
 __global__ void k_reset_counter(uint32_t* counter) { *counter = 0u; }
 
+// One out-of-line function per (format, tile): each path gets its own register
+// allocation instead of the union of all paths inlined into one body.
+template <class F, class TILE>
+__device__ __noinline__ void run_tile(GemvArgs a, int64_t row0)
+{
+    gemv_block<F, TILE>(a, row0);
+}
+
 template <int B, int K>
 __device__ __forceinline__ void run_format(const DescDev& d, int slot, int64_t row0)
 {
     using F = Fmt<B, K>;
     switch (slot) {
-        case 0: gemv_block<F, GemvTile<64, 2, 2>>(d.a, row0); break;   // config 2
-        case 1: gemv_block<F, GemvTile<64, 2, 4>>(d.a, row0); break;   // config 3
-        case 2: gemv_block<F, GemvTile<64, 4, 2>>(d.a, row0); break;   // config 5
-        case 3: gemv_block<F, GemvTile<32, 2, 2>>(d.a, row0); break;   // config 7
-        case 4: gemv_block<F, GemvTile<16, 2, 2>>(d.a, row0); break;   // config 9
-        default: gemv_block<F, GemvTile<8, 2, 1>>(d.a, row0); break;   // config 11
+        case 0: run_tile<F, GemvTile<8, 2, 1>>(d.a, row0); break;              // config 11
+        case 1: run_tile<F, GemvTile<8, 4, 1>>(d.a, row0); break;              // config 12
+        case 2: run_tile<F, GemvTile<16, 2, 2>>(d.a, row0); break;             // config 9
+        case 3: run_tile<F, GemvTile<16, 4, 1>>(d.a, row0); break;             // config 10
+        case 4: run_tile<F, GemvTile<8, 2, 1, 1, true>>(d.a, row0); break;     // config 33
+        case 5: run_tile<F, GemvTile<16, 2, 2, 1, true>>(d.a, row0); break;    // config 32
+        case 6: run_tile<F, GemvTile<64, 4, 1, 2, true>>(d.a, row0); break;    // config 21
+        default: run_tile<F, GemvTile<32, 2, 2>>(d.a, row0); break;            // config 7
     }
 }
 
-__global__ void __launch_bounds__(kGemvBlock)
+__global__ void __launch_bounds__(kGemvBlock, 3)
 k_gemv_batched(const DescDev* __restrict__ descs, const WorkItem* __restrict__ items, int32_t nitems,
                uint32_t* __restrict__ counter)
 {
@@ -149,19 +161,34 @@ static void plan_free_device(fb_plan* p)
     p->d_counter = nullptr;
 }
 
+// Untuned choice inside the persistent kernel: few lanes per row (many rows
+// per work item) measured fastest for rows of up to a few thousand elements.
 static int pick_batched_tile(const fb_gemv_desc& d)
 {
     const int t = tune_lookup(d.f, d.m, d.n);
     if (t >= 0 && batched_slot(t) >= 0) return t;
-    const int def = gemv_default_tile(d.m, d.n, d.f.k);
-    return batched_slot(def) >= 0 ? def : 2;
+    return 11;
 }
 
-// Builds (or rebuilds) the device tables from p->descs and p->tiles.
-static fb_status plan_upload(fb_plan* p)
+// Device tables of a set of descriptors with their tiles: descriptor table,
+// work items (longest first) and the persistent grid size.
+struct Tables {
+    DescDev* d_descs = nullptr;
+    WorkItem* d_items = nullptr;
+    int32_t nitems = 0;
+    int grid = 0;
+};
+
+static void free_tables(Tables& t)
 {
-    plan_free_device(p);
-    const int count = (int)p->descs.size();
+    if (t.d_descs) (void)hipFree(t.d_descs);
+    if (t.d_items) (void)hipFree(t.d_items);
+    t = Tables{};
+}
+
+static fb_status build_tables(const std::vector<fb_gemv_desc>& descs, const std::vector<int>& tiles, Tables& out)
+{
+    const int count = (int)descs.size();
     std::vector<DescDev> dd(count);
     struct Run {
         int desc;
@@ -173,8 +200,8 @@ static fb_status plan_upload(fb_plan* p)
     runs.reserve(count);
     int64_t total_items = 0;
     for (int i = 0; i < count; ++i) {
-        const fb_gemv_desc& d = p->descs[i];
-        const int tile = p->tiles[i];
+        const fb_gemv_desc& d = descs[i];
+        const int tile = tiles[i];
         const TileInfo ti = gemv_tile_info(tile);
         dd[i].a = GemvArgs{static_cast<const uint8_t*>(d.A), d.lda * d.f.k, d.x, d.y, d.m, d.n};
         dd[i].code = format_index(d.f) * kBatchedNumTiles + batched_slot(tile);
@@ -185,24 +212,21 @@ static fb_status plan_upload(fb_plan* p)
         total_items += nt;
     }
     if (total_items > INT32_MAX - 1024) return set_error(FB_ERR_ARG, "fb_gemv_batched_plan: too many work items");
-    // longest work items first
     std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.cost > b.cost; });
     std::vector<WorkItem> items;
     items.reserve((size_t)total_items);
     for (const Run& r : runs)
         for (int t = 0; t < r.nt; ++t) items.push_back(WorkItem{r.desc, t * r.rows_per_block});
-    p->nitems = (int32_t)items.size();
-
-    if (hipMalloc(&p->d_descs, sizeof(DescDev) * std::max(1, count)) != hipSuccess ||
-        hipMalloc(&p->d_items, sizeof(WorkItem) * std::max<size_t>(1, items.size())) != hipSuccess ||
-        hipMalloc(&p->d_counter, 256) != hipSuccess) {
-        plan_free_device(p);
+    out.nitems = (int32_t)items.size();
+    if (hipMalloc(&out.d_descs, sizeof(DescDev) * std::max(1, count)) != hipSuccess ||
+        hipMalloc(&out.d_items, sizeof(WorkItem) * std::max<size_t>(1, items.size())) != hipSuccess) {
+        free_tables(out);
         return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_plan: device allocation failed");
     }
-    if ((count && hipMemcpy(p->d_descs, dd.data(), sizeof(DescDev) * count, hipMemcpyHostToDevice) != hipSuccess) ||
+    if ((count && hipMemcpy(out.d_descs, dd.data(), sizeof(DescDev) * count, hipMemcpyHostToDevice) != hipSuccess) ||
         (!items.empty() &&
-         hipMemcpy(p->d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)) {
-        plan_free_device(p);
+         hipMemcpy(out.d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+        free_tables(out);
         return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_plan: upload failed");
     }
     int per_cu = 0;
@@ -210,7 +234,25 @@ static fb_status plan_upload(fb_plan* p)
                                                      kGemvBlock, 0) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
-    p->grid = std::max(1, std::min<int>(per_cu * device_cu_count(), std::max<int32_t>(1, p->nitems)));
+    out.grid = std::max(1, std::min<int>(per_cu * device_cu_count(), std::max<int32_t>(1, out.nitems)));
+    return FB_OK;
+}
+
+// Builds (or rebuilds) the plan's device tables from p->descs and p->tiles.
+static fb_status plan_upload(fb_plan* p)
+{
+    plan_free_device(p);
+    Tables t;
+    fb_status st = build_tables(p->descs, p->tiles, t);
+    if (st != FB_OK) return st;
+    if (hipMalloc(&p->d_counter, 256) != hipSuccess) {
+        free_tables(t);
+        return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_plan: device allocation failed");
+    }
+    p->d_descs = t.d_descs;
+    p->d_items = t.d_items;
+    p->nitems = t.nitems;
+    p->grid = t.grid;
     return FB_OK;
 }
 
@@ -306,34 +348,45 @@ extern "C" fb_status fb_gemv_batched_tune(fb_plan* plan, int32_t reps, hipStream
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_tune: hipEventCreate failed");
+    uint32_t* counter = nullptr;
+    if (hipMalloc(&counter, 256) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_tune: allocation failed");
+    }
     fb_status result = FB_OK;
     for (size_t g0 = 0; g0 < order.size() && result == FB_OK;) {
         size_t g1 = g0;
         while (g1 < order.size() && !(order[g0].first < order[g1].first) && !(order[g1].first < order[g0].first)) ++g1;
-        const size_t members = std::min<size_t>(g1 - g0, 16);
+        // the group's GEMVs (up to 64) run alone in the persistent kernel with each candidate tile
+        std::vector<fb_gemv_desc> sub;
+        for (size_t j = g0; j < g1 && sub.size() < 64; ++j) sub.push_back(plan->descs[order[j].second]);
         int best = -1;
         double best_us = 1e300;
         for (int s = 0; s < kBatchedNumTiles && result == FB_OK; ++s) {
-            const int tile = kBatchedTile[s];
-            auto pass = [&]() {
-                for (size_t j = g0; j < g0 + members && result == FB_OK; ++j) {
-                    const fb_gemv_desc& d = plan->descs[order[j].second];
-                    result = gemv_launch_tile(d.f, d.m, d.n, d.A, d.lda, d.x, d.y, tile, stream);
-                }
+            std::vector<int> tiles(sub.size(), kBatchedTile[s]);
+            Tables t;
+            result = build_tables(sub, tiles, t);
+            if (result != FB_OK) break;
+            auto run = [&]() {
+                k_reset_counter<<<1, 1, 0, stream>>>(counter);
+                k_gemv_batched<<<t.grid, kGemvBlock, 0, stream>>>(t.d_descs, t.d_items, t.nitems, counter);
             };
-            pass();
+            run();
             float ms = 0.f;
-            if (result != FB_OK || hipEventRecord(e0, stream) != hipSuccess) break;
-            for (int r = 0; r < reps && result == FB_OK; ++r) pass();
-            if (result != FB_OK || hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                if (result == FB_OK) result = set_error(FB_ERR_RUNTIME, "fb_gemv_batched_tune: timing failed");
+            bool ok = hipEventRecord(e0, stream) == hipSuccess;
+            for (int r = 0; r < reps && ok; ++r) run();
+            ok = ok && hipGetLastError() == hipSuccess && hipEventRecord(e1, stream) == hipSuccess &&
+                 hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            free_tables(t);
+            if (!ok) {
+                result = set_error(FB_ERR_RUNTIME, "fb_gemv_batched_tune: timing failed");
                 break;
             }
-            const double us = 1000.0 * ms / (reps * (double)members);
+            const double us = 1000.0 * ms / reps;
             if (us < best_us) {
                 best_us = us;
-                best = tile;
+                best = kBatchedTile[s];
             }
         }
         if (result == FB_OK && best >= 0) {
@@ -343,10 +396,11 @@ extern "C" fb_status fb_gemv_batched_tune(fb_plan* plan, int32_t reps, hipStream
         }
         g0 = g1;
     }
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(counter);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (result != FB_OK) return result;
-    if (hipStreamSynchronize(stream) != hipSuccess) return set_error(FB_ERR_RUNTIME, "fb_gemv_batched_tune: sync");
     return plan_upload(plan);
 }
 

@@ -253,9 +253,12 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
     X(27, 64, 4, 1, 2, true, true)          \
     X(28, 64, 2, 1, 4, true, true)          \
     X(29, 64, 4, 1, 4, true, true)          \
-    X(30, 64, 8, 1, 4, true, true)
+    X(30, 64, 8, 1, 4, true, true)          \
+    X(31, 32, 2, 2, 1, true, false)         \
+    X(32, 16, 2, 2, 1, true, false)         \
+    X(33, 8, 2, 1, 1, true, false)
 
-constexpr int kGemvNumTiles = 31;
+constexpr int kGemvNumTiles = 34;
 
 struct TileInfo {
     int lpr, rpw, u, ks, nt, staged, rows_per_block;

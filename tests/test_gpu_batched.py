@@ -123,7 +123,7 @@ def test_batched_tuned_plan(dev):
     torch.cuda.synchronize()
     for i, it in enumerate(items):
         assert same_bits(it.y, ref[i]), (i, plan.config(i))
-    assert all(plan.config(i) in (2, 3, 5, 7, 9, 11) for i in range(len(items)))
+    assert all(plan.config(i) in (11, 12, 9, 10, 33, 32, 21, 7) for i in range(len(items)))
     plan.close()
 
 
