@@ -72,6 +72,12 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "fbo_gemm_naive": (None, [c_int, c_int, c_int, c_int, c_i64, c_i64, c_i64, c_p, c_i64,
                                   c_p, c_i64, c_p, c_i64]),
         "fbo_mutation": (c_int, []),
+        "fbo_pack_bits_mode": (c_u64, [c_int, c_int, c_u64, c_int]),
+        "fbo_pack_mode": (None, [c_int, c_int, c_int, c_p, c_p, c_sz]),
+        "fbo_axpy_mode": (None, [c_int, c_int, c_int, c_sz, c_dbl, c_p, c_p]),
+        "fbo_scale": (None, [c_int, c_int, c_int, c_sz, c_dbl, c_p]),
+        "fbo_nrm2_naive": (c_dbl, [c_int, c_int, c_sz, c_p]),
+        "fbo_nrm2_exact": (c_dbl, [c_int, c_int, c_sz, c_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -124,13 +130,21 @@ class Oracle:
     def mant_bits(self, base: int, k: int) -> int:
         return int(self.lib.fbo_mant_bits(base, k))
 
+    def pack_bits_mode(self, base: int, k: int, u: int, mode: int) -> int:
+        return int(self.lib.fbo_pack_bits_mode(base, k, int(u), mode))
+
     # -- arrays ---------------------------------------------------------
-    def pack(self, base: int, k: int, native: np.ndarray) -> np.ndarray:
-        """native (float32/float64 or same-width uint bit patterns) -> uint8[n*k]."""
+    def pack(self, base: int, k: int, native: np.ndarray, mode: int = 0) -> np.ndarray:
+        """native (float32/float64 or same-width uint bit patterns) -> uint8[n*k].
+
+        mode: 0 round to nearest even, 1 toward zero, 2 to odd."""
         check_format(base, k)
         src = np.ascontiguousarray(native).view(_bits_dtype(base)).reshape(-1)
         out = np.empty(src.size * k, dtype=np.uint8)
-        self.lib.fbo_pack(base, k, _ptr(src), _ptr(out), src.size)
+        if mode == 0:
+            self.lib.fbo_pack(base, k, _ptr(src), _ptr(out), src.size)
+        else:
+            self.lib.fbo_pack_mode(base, k, mode, _ptr(src), _ptr(out), src.size)
         return out
 
     def unpack(self, base: int, k: int, packed: np.ndarray, n: int | None = None) -> np.ndarray:
@@ -153,13 +167,30 @@ class Oracle:
             q |= b[:, j] << np.uint64(8 * j)
         return q
 
-    def axpy(self, base: int, k: int, alpha: float, x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    def axpy(self, base: int, k: int, alpha: float, x: np.ndarray, y: np.ndarray, mode: int = 0) -> np.ndarray:
         """Returns a new packed y <- pack(fma(alpha, x, y))."""
         x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
         yy = np.array(y, dtype=np.uint8, copy=True).reshape(-1)
         n = yy.size // k
-        self.lib.fbo_axpy(base, k, n, float(alpha), _ptr(x), _ptr(yy))
+        if mode == 0:
+            self.lib.fbo_axpy(base, k, n, float(alpha), _ptr(x), _ptr(yy))
+        else:
+            self.lib.fbo_axpy_mode(base, k, mode, n, float(alpha), _ptr(x), _ptr(yy))
         return yy
+
+    def scale(self, base: int, k: int, alpha: float, x: np.ndarray, mode: int = 0) -> np.ndarray:
+        """Returns a new packed x <- pack(alpha * x)."""
+        xx = np.array(x, dtype=np.uint8, copy=True).reshape(-1)
+        self.lib.fbo_scale(base, k, mode, xx.size // k, float(alpha), _ptr(xx))
+        return xx
+
+    def nrm2_naive(self, base: int, k: int, x: np.ndarray) -> float:
+        x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
+        return float(self.lib.fbo_nrm2_naive(base, k, x.size // k, _ptr(x)))
+
+    def nrm2_exact(self, base: int, k: int, x: np.ndarray) -> float:
+        x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
+        return float(self.lib.fbo_nrm2_exact(base, k, x.size // k, _ptr(x)))
 
     def dot_naive(self, base: int, k: int, x: np.ndarray, y: np.ndarray) -> float:
         x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)

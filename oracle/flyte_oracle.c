@@ -28,6 +28,9 @@
  *     sign is kept (Section 5.3, NaN values; Section 5.1 for truncation of
  *     quiet NaNs).
  *   - binary64 with k = 2, 3, 4 follows the same rule, m = 8k - 12.
+ *   - Rounding modes other than nearest-even (Section 5.1 round toward zero;
+ *     Section 7 round to odd after Boldo and Melquiond) decide only the
+ *     finite/infinite inputs; NaNs follow the same NaN rule in every mode.
  *
  * Build: plain C11, compiled with -O2 -ffp-contract=off so that every fused
  * multiply-add below is the explicit fma()/fmaf() call and nothing else.
@@ -39,6 +42,7 @@
  *   3 = the add-half-ULP heuristic of Section 5.2 (no tie rule, no NaN fix)
  *   4 = unpack shifts by one byte too few (wrong alignment of stored bytes)
  *   5 = sign bit lost on pack
+ *   6 = round to odd that never sets the lowest bit (plain truncation)
  */
 #include <math.h>
 #include <stdint.h>
@@ -153,6 +157,41 @@ uint64_t fbo_pack_bits(int base, int k, uint64_t u)
 }
 
 /* ------------------------------------------------------------------ */
+/* Pack with a rounding mode: 0 nearest even (above), 1 toward zero      */
+/* (Section 5.1: drop the low bytes), 2 to odd (Section 7: drop the low  */
+/* bytes and, if any dropped bit was set, force the lowest kept bit to   */
+/* 1).  NaNs are handled as in the nearest-even pack.                    */
+/* ------------------------------------------------------------------ */
+enum { FBO_RNE = 0, FBO_RTZ = 1, FBO_RTO = 2 };
+
+uint64_t fbo_pack_bits_mode(int base, int k, uint64_t u, int mode)
+{
+    if (mode == FBO_RNE) return fbo_pack_bits(base, k, u);
+    const int W = base;
+    const int E = exp_bits(base);
+    const int d = W - 8 * k;
+    const int m = 8 * k - 1 - E;
+    u &= low_mask(W);
+    if (d == 0) return u;
+    const uint64_t expo = (u >> (W - 1 - E)) & low_mask(E);
+    const uint64_t frac = u & low_mask(W - 1 - E);
+    uint64_t q = u >> d;
+    if (expo == low_mask(E) && frac != 0) {          /* NaN */
+        if ((q & low_mask(m)) == 0) q |= (uint64_t)1 << (m - 1);
+        return q;
+    }
+    if (mode == FBO_RTO) {
+        const int inexact = (u & low_mask(d)) != 0;
+#if FBO_MUTATION == 6
+        (void)inexact;
+#else
+        if (inexact) q |= 1;                          /* the odd neighbour */
+#endif
+    }
+    return q;                                         /* toward zero: truncation */
+}
+
+/* ------------------------------------------------------------------ */
 /* Arrays of packed elements (Section 4.1: consecutive, no padding).    */
 /* ------------------------------------------------------------------ */
 static uint64_t load_elem(const uint8_t *p, int k, size_t i)
@@ -193,6 +232,12 @@ void fbo_pack(int base, int k, const void *src, uint8_t *dst, size_t n)
         store_elem(dst, k, i, fbo_pack_bits(base, k, load_native_bits(src, base, i)));
 }
 
+void fbo_pack_mode(int base, int k, int mode, const void *src, uint8_t *dst, size_t n)
+{
+    for (size_t i = 0; i < n; ++i)
+        store_elem(dst, k, i, fbo_pack_bits_mode(base, k, load_native_bits(src, base, i), mode));
+}
+
 static double elem_value(int base, int k, const uint8_t *p, size_t i)
 {
     uint64_t u = fbo_unpack_bits(base, k, load_elem(p, k, i));
@@ -225,6 +270,32 @@ void fbo_axpy(int base, int k, size_t n, double alpha, const uint8_t *x, uint8_t
             r = bits_of_double(fma(alpha, xi, yi));
         }
         store_elem(y, k, i, fbo_pack_bits(base, k, r));
+    }
+}
+
+void fbo_axpy_mode(int base, int k, int mode, size_t n, double alpha, const uint8_t *x, uint8_t *y)
+{
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t r;
+        if (base == 32) {
+            float a = (float)alpha;
+            r = bits_of_float(fmaf(a, (float)elem_value(base, k, x, i), (float)elem_value(base, k, y, i)));
+        } else {
+            r = bits_of_double(fma(alpha, elem_value(base, k, x, i), elem_value(base, k, y, i)));
+        }
+        store_elem(y, k, i, fbo_pack_bits_mode(base, k, r, mode));
+    }
+}
+
+/* The paper's in-place BLAS-1 "scale" program: x[i] <- pack(alpha * x[i]),
+ * one multiplication in the base type (alpha first rounded to it). */
+void fbo_scale(int base, int k, int mode, size_t n, double alpha, uint8_t *x)
+{
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t r;
+        if (base == 32) r = bits_of_float((float)alpha * (float)elem_value(base, k, x, i));
+        else r = bits_of_double(alpha * elem_value(base, k, x, i));
+        store_elem(x, k, i, fbo_pack_bits_mode(base, k, r, mode));
     }
 }
 
@@ -372,6 +443,35 @@ double fbo_dot_exact(int base, int k, size_t n, const uint8_t *x, const uint8_t 
     for (size_t i = 0; i < n; ++i) acc_add_product(&a, elem_value(base, k, x, i), elem_value(base, k, y, i));
     if (base == 32) return (double)(float)acc_round(&a, 24, -126, 127);
     return acc_round(&a, 53, -1022, 1023);
+}
+
+/* "magnitude": the Euclidean norm sqrt(sum x_i^2) of a packed vector.
+ * naive: sequential fma of squares in the base type, then sqrt in it;
+ * exact: the sum of squares exactly (long accumulator), rounded once to the
+ * base type, then its correctly rounded square root. */
+double fbo_nrm2_naive(int base, int k, size_t n, const uint8_t *x)
+{
+    if (base == 32) {
+        float s = 0.0f;
+        for (size_t i = 0; i < n; ++i) {
+            float v = (float)elem_value(base, k, x, i);
+            s = fmaf(v, v, s);
+        }
+        return (double)sqrtf(s);
+    }
+    double s = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+        double v = elem_value(base, k, x, i);
+        s = fma(v, v, s);
+    }
+    return sqrt(s);
+}
+
+double fbo_nrm2_exact(int base, int k, size_t n, const uint8_t *x)
+{
+    double s2 = fbo_dot_exact(base, k, n, x, x);
+    if (base == 32) return (double)sqrtf((float)s2);
+    return sqrt(s2);
 }
 
 /* Exact dot of two native double vectors with strides (for GEMM columns);

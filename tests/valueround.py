@@ -111,6 +111,38 @@ def expected_pack(base: int, k: int, u: int):
     return encode(base, k, round_rne(val, m + 1, emin, emax), neg)
 
 
+def round_directed(v: Fraction, p: int, emin: int, mode: int):
+    """Round toward zero (mode 1) or to odd (mode 2) with precision p and minimum
+    normal exponent emin (gradual underflow); never overflows."""
+    if v == 0:
+        return Fraction(0)
+    neg = v < 0
+    a = -v if neg else v
+    e = floor_log2(a)
+    s = max(e, emin) - (p - 1)
+    scale = Fraction(2) ** s
+    q = a / scale
+    n = q.numerator // q.denominator
+    if mode == 2 and n * scale != a and n % 2 == 0:
+        n += 1
+    r = n * scale
+    return -r if neg else r
+
+
+def expected_pack_mode(base: int, k: int, u: int, mode: int):
+    """Expected k-byte pattern for a non-NaN input in rounding mode 0, 1 or 2."""
+    if mode == 0:
+        return expected_pack(base, k, u)
+    val = decode(base, u)
+    neg = bool((u >> (base - 1)) & 1)
+    if val == "nan":
+        return None
+    E, m, bias, emin, emax = params(base, k)
+    if val in (INF, NINF):
+        return encode(base, k, val, neg)
+    return encode(base, k, round_directed(val, m + 1, emin, mode), neg)
+
+
 def round_to_base(v, base: int):
     """Round an exact rational to binary32/binary64 (nearest even); INF/NINF on overflow."""
     if base == 32:
