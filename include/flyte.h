@@ -20,10 +20,11 @@
  * the dropped bytes with zeros (Section 3.2).  pack rounds to nearest, ties to
  * even, at the cut (Section 5.2), with the increment carrying into the
  * exponent: values round up into the next binade, the largest finite values
- * can round to infinity, subnormals underflow gradually (Section 5.3).  A NaN
- * is truncated and, if that leaves its kept mantissa zero, gets the quiet bit
- * (the top kept mantissa bit), so NaN stays NaN with its sign.  Denormals are
- * never flushed.
+ * can round to infinity, subnormals underflow gradually (Section 5.3); the
+ * format's round field can select round toward zero or round to odd instead.
+ * In every mode a NaN is truncated and, if that leaves its kept mantissa
+ * zero, gets the quiet bit (the top kept mantissa bit), so NaN stays NaN with
+ * its sign.  Denormals are never flushed.
  *
  * Arithmetic (Section 3.1, and the AT_LEAST accumulator and FP_CONTRACT of
  * Section 4.4): every operation computes in the base type -- binary32 formats
@@ -57,10 +58,22 @@
 extern "C" {
 #endif
 
-/* Format descriptor {base, k}: base 32 with k in 2..4, or base 64 with k in 2..8. */
+/* Format descriptor {base, k, round}: base 32 with k in 2..4, or base 64 with
+ * k in 2..8.  round selects how values are cut to k bytes wherever a call
+ * packs results (fb_pack, fb_axpy, fb_scale, a packed fb_gemm C); it is
+ * ignored by calls that only read packed data.  reserved must be 0. */
+typedef enum fb_round {
+    FB_ROUND_NEAREST_EVEN = 0,   /* Section 5.2 (the default) */
+    FB_ROUND_TOWARD_ZERO = 1,    /* Section 5.1: drop the low bytes */
+    FB_ROUND_TO_ODD = 2          /* Section 7 (Boldo-Melquiond): drop the low bytes, set the
+                                    lowest kept bit if any dropped bit was set */
+} fb_round;
+
 typedef struct fb_format {
     uint8_t base;
     uint8_t k;
+    uint8_t round;      /* fb_round */
+    uint8_t reserved;
 } fb_format;
 
 typedef enum fb_status {
@@ -98,6 +111,17 @@ fb_status fb_dot(fb_format f, size_t n, const void *x, const void *y, void *resu
  * x and y are packed (n*k bytes); x must not overlap y. */
 fb_status fb_axpy(fb_format f, size_t n, double alpha, const void *x, void *y,
                   hipStream_t stream);
+
+/* x_i <- pack(alpha * unpack(x_i)), in place (the paper's BLAS-1 "scale"
+ * program, Section 6): one multiplication in the base type, alpha first
+ * rounded to it, then the cut in the format's rounding mode.  Bit-exact. */
+fb_status fb_scale(fb_format f, size_t n, double alpha, void *x, hipStream_t stream);
+
+/* result = sqrt(sum_i unpack(x_i)^2) (the vector "magnitude"): squares summed
+ * with fma in the base type in a fixed order, then one square root in it.
+ * No rescaling: squares that overflow the base type give Inf.  result: one
+ * native value in device memory. */
+fb_status fb_nrm2(fb_format f, size_t n, const void *x, void *result, hipStream_t stream);
 
 /* ------------------------------------------------------------------ BLAS 2 */
 
@@ -149,7 +173,6 @@ void fb_tune_clear(void);
 /* One independent GEMV y = A x of a batch (same semantics as fb_gemv). */
 typedef struct fb_gemv_desc {
     fb_format f;
-    uint16_t reserved0;
     int32_t m;
     int32_t n;
     int32_t reserved1;
@@ -211,7 +234,7 @@ void fb_plan_destroy(fb_plan *plan);
  *    lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
  *  - fa = fb = {64,5} or {64,6}, fc any binary64 format: operands unpacked to
  *    FP64, FP64 matrix-core products and accumulation, C rounded to fc in the
- *    epilogue (one rounding of the FP64 result, Section 5.2).
+ *    epilogue in fc's rounding mode (one rounding of the FP64 result).
  * M, N, K >= 0; M and N must be multiples of 4 for a packed C with k < 8. */
 fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
                   const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,

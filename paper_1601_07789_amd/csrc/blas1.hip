@@ -1,4 +1,6 @@
-// Streaming kernels over packed arrays: pack, unpack, axpy and dot.
+// Streaming kernels over packed arrays: pack, unpack, axpy, scale, dot and
+// the vector magnitude (norm).  Kernels that produce packed values take the
+// rounding mode of the format as a template parameter.
 //
 // Every kernel walks the array in units of F::UNIT elements (whole dwords of
 // packed data).  Thread t of a grid of T threads handles units t, t + T, ...,
@@ -17,7 +19,7 @@ constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
 // ---------------------------------------------------------------- pack
-template <class F, int U>
+template <class F, int MODE, int U>
 __global__ void __launch_bounds__(kBlock)
 k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
 {
@@ -38,7 +40,7 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
                 T b[F::UNIT];
                 words_to_bits<F, F::UNIT>(w[u], b);
 #pragma unroll
-                for (int e = 0; e < F::UNIT; ++e) b[e] = rne_pack<F>(b[e]);
+                for (int e = 0; e < F::UNIT; ++e) b[e] = round_pack<F, MODE>(b[e]);
                 uint32_t P[F::UNIT_DW];
                 assemble_elems<F, F::UNIT>(b, P);
                 store_dwords(dst + g * F::UNIT_DW, P);
@@ -51,7 +53,7 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
             T u;
             if constexpr (F::W == 4) u = src[i];
             else u = (uint64_t(src[2 * i + 1]) << 32) | src[2 * i];
-            store_elem_bytes<F>(reinterpret_cast<uint8_t*>(dst) + i * F::k, rne_pack<F>(u));
+            store_elem_bytes<F>(reinterpret_cast<uint8_t*>(dst) + i * F::k, round_pack<F, MODE>(u));
         }
     }
 }
@@ -98,7 +100,7 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
 }
 
 // ---------------------------------------------------------------- axpy
-template <class F, int U>
+template <class F, int MODE, int U>
 __global__ void __launch_bounds__(kBlock)
 k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __restrict__ y, int64_t nunits,
        int64_t n)
@@ -125,7 +127,7 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
                 unpack_elems<F, F::UNIT>(PY[u], by);
 #pragma unroll
                 for (int e = 0; e < F::UNIT; ++e)
-                    by[e] = rne_pack<F>(as_bits<F>(fma_n(alpha, as_native<F>(bx[e]), as_native<F>(by[e]))));
+                    by[e] = round_pack<F, MODE>(as_bits<F>(fma_n(alpha, as_native<F>(bx[e]), as_native<F>(by[e]))));
                 uint32_t P[F::UNIT_DW];
                 assemble_elems<F, F::UNIT>(by, P);
                 store_dwords(y + g * F::UNIT_DW, P);
@@ -139,7 +141,45 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
             uint8_t* yb = reinterpret_cast<uint8_t*>(y) + i * F::k;
             const auto r = fma_n(alpha, as_native<F>(load_elem_unpacked<F>(xb)),
                                  as_native<F>(load_elem_unpacked<F>(yb)));
-            store_elem_bytes<F>(yb, rne_pack<F>(as_bits<F>(r)));
+            store_elem_bytes<F>(yb, round_pack<F, MODE>(as_bits<F>(r)));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- scale (in place)
+template <class F, int MODE, int U>
+__global__ void __launch_bounds__(kBlock)
+k_scale(typename F::native_t alpha, uint32_t* __restrict__ x, int64_t nunits, int64_t n)
+{
+    using T = typename F::bits_t;
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
+        uint32_t PX[U][F::UNIT_DW];
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) load_dwords(x + g * F::UNIT_DW, PX[u]);
+        });
+        static_for<U>([&](auto iu) {
+            constexpr int u = decltype(iu)::value;
+            const int64_t g = g0 + u * nthreads;
+            if (g < nunits) {
+                T bx[F::UNIT];
+                unpack_elems<F, F::UNIT>(PX[u], bx);
+#pragma unroll
+                for (int e = 0; e < F::UNIT; ++e) bx[e] = round_pack<F, MODE>(as_bits<F>(alpha * as_native<F>(bx[e])));
+                uint32_t P[F::UNIT_DW];
+                assemble_elems<F, F::UNIT>(bx, P);
+                store_dwords(x + g * F::UNIT_DW, P);
+            }
+        });
+    }
+    if (blockIdx.x == 0) {
+        const int64_t i = nunits * F::UNIT + threadIdx.x;
+        if (threadIdx.x < F::UNIT && i < n) {
+            uint8_t* xb = reinterpret_cast<uint8_t*>(x) + i * F::k;
+            store_elem_bytes<F>(xb, round_pack<F, MODE>(as_bits<F>(alpha * as_native<F>(load_elem_unpacked<F>(xb)))));
         }
     }
 }
@@ -211,13 +251,21 @@ k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, in
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-template <class N>
+template <class N, bool SQRT>
 __global__ void __launch_bounds__(kBlock) k_dot_final(const N* __restrict__ partials, int nparts, N* __restrict__ out)
 {
     N acc = N(0);
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc = acc + partials[i];
     const N s = block_sum(acc);
-    if (threadIdx.x == 0) *out = s;
+    if (threadIdx.x == 0) {
+        if constexpr (SQRT) {
+            // one correctly rounded square root in the base type
+            if constexpr (sizeof(N) == 4) *out = __builtin_sqrtf(s);
+            else *out = __builtin_sqrt(s);
+        } else {
+            *out = s;
+        }
+    }
 }
 
 template <class N>
@@ -283,9 +331,11 @@ extern "C" fb_status fb_pack(fb_format f, const void* src_native, void* dst_pack
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         const int64_t nunits = (int64_t)(n / F::UNIT);
-        k_pack<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
-            static_cast<const uint32_t*>(src_native), static_cast<uint32_t*>(dst_packed), nunits, (int64_t)n);
-        return check_launch("fb_pack");
+        return dispatch_round(f, [&](auto rt) {
+            k_pack<F, decltype(rt)::value, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+                static_cast<const uint32_t*>(src_native), static_cast<uint32_t*>(dst_packed), nunits, (int64_t)n);
+            return check_launch("fb_pack");
+        });
     });
 }
 
@@ -310,9 +360,11 @@ extern "C" fb_status fb_axpy(fb_format f, size_t n, double alpha, const void* x,
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         using N = typename F::native_t;
         const int64_t nunits = (int64_t)(n / F::UNIT);
-        k_axpy<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
-            (N)alpha, static_cast<const uint32_t*>(x), static_cast<uint32_t*>(y), nunits, (int64_t)n);
-        return check_launch("fb_axpy");
+        return dispatch_round(f, [&](auto rt) {
+            k_axpy<F, decltype(rt)::value, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+                (N)alpha, static_cast<const uint32_t*>(x), static_cast<uint32_t*>(y), nunits, (int64_t)n);
+            return check_launch("fb_axpy");
+        });
     });
 }
 
@@ -338,7 +390,50 @@ extern "C" fb_status fb_dot(fb_format f, size_t n, const void* x, const void* y,
         k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
                                                                static_cast<const uint32_t*>(y), nunits,
                                                                (int64_t)n, static_cast<N*>(ws));
-        k_dot_final<N><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
+        k_dot_final<N, false><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
         return check_launch("fb_dot");
+    });
+}
+
+extern "C" fb_status fb_nrm2(fb_format f, size_t n, const void* x, void* result, hipStream_t stream)
+{
+    if (!result) return set_error(FB_ERR_ARG, "fb_nrm2: null result");
+    if (!aligned4(result)) return set_error(FB_ERR_ALIGN, "fb_nrm2: result must be 4-byte aligned");
+    fb_status st = check_vec("fb_nrm2", f, x, x, n);
+    if (st != FB_OK) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        using N = typename F::native_t;
+        if (n == 0) {
+            k_store_zero<N><<<1, 1, 0, stream>>>(static_cast<N*>(result));
+            return check_launch("fb_nrm2");
+        }
+        void* ws = nullptr;
+        fb_status s2 = dot_workspace(stream, &ws);
+        if (s2 != FB_OK) return s2;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        int grid = stream_grid(nunits, kUnroll);
+        if (grid > kMaxDotBlocks) grid = kMaxDotBlocks;
+        k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
+                                                               static_cast<const uint32_t*>(x), nunits,
+                                                               (int64_t)n, static_cast<N*>(ws));
+        k_dot_final<N, true><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
+        return check_launch("fb_nrm2");
+    });
+}
+
+extern "C" fb_status fb_scale(fb_format f, size_t n, double alpha, void* x, hipStream_t stream)
+{
+    fb_status st = check_vec("fb_scale", f, x, x, n);
+    if (st != FB_OK || n == 0) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        using N = typename F::native_t;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        return dispatch_round(f, [&](auto rt) {
+            k_scale<F, decltype(rt)::value, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+                (N)alpha, static_cast<uint32_t*>(x), nunits, (int64_t)n);
+            return check_launch("fb_scale");
+        });
     });
 }

@@ -173,6 +173,30 @@ __device__ __forceinline__ typename F::bits_t rne_pack(typename F::bits_t u)
     }
 }
 
+// Pack in a rounding mode: 0 nearest even (above), 1 toward zero (drop the
+// low bytes; Section 5.1), 2 to odd (drop them and set the lowest kept bit if
+// any dropped bit was set; Section 7).  NaNs take the same rule in every mode.
+template <class F, int MODE>
+__device__ __forceinline__ typename F::bits_t round_pack(typename F::bits_t u)
+{
+    using T = typename F::bits_t;
+    if constexpr (MODE == 0 || F::D == 0) {
+        return rne_pack<F>(u);
+    } else {
+        constexpr T one = 1;
+        constexpr T abs_mask = (one << (F::base - 1)) - 1;
+        constexpr T inf_bits = ((one << F::E) - 1) << (F::base - 1 - F::E);
+        constexpr T kept_mant = (one << F::M) - 1;
+        constexpr T quiet = one << (F::M - 1);
+        constexpr T dropped = (one << F::D) - 1;
+        const T q = u >> F::D;
+        const T qn = ((q & kept_mant) == 0) ? (q | quiet) : q;
+        T r = q;
+        if constexpr (MODE == 2) r = q | (T)((u & dropped) != 0);
+        return ((u & abs_mask) > inf_bits) ? qn : r;
+    }
+}
+
 // Stream byte that holds byte bi of packed element e, when the packed values
 // sit one per native word (low k bytes of a 4- or 8-byte word).
 template <class F>

@@ -18,9 +18,24 @@ void clear_error();
 
 inline bool format_ok(fb_format f)
 {
+    if (f.round > 2 || f.reserved != 0) return false;
     if (f.base == 32) return f.k >= 2 && f.k <= 4;
     if (f.base == 64) return f.k >= 2 && f.k <= 8;
     return false;
+}
+
+template <int R>
+using round_tag = std::integral_constant<int, R>;
+
+// Calls fn(round_tag<mode>{}) for the runtime rounding mode of f.
+template <class Fn>
+auto dispatch_round(fb_format f, Fn&& fn)
+{
+    switch (f.round) {
+        case 1: return fn(round_tag<1>{});
+        case 2: return fn(round_tag<2>{});
+        default: return fn(round_tag<0>{});
+    }
 }
 
 inline bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }

@@ -52,7 +52,7 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <int KIN, int KOUT>
+template <int KIN, int KOUT, int MODE>
 __global__ void __launch_bounds__(GD_THREADS, 2)
 k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K)
@@ -158,7 +158,7 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
                 const int col = n0 + wn * 64 + j * 16 + c16;
-                const uint64_t q = rne_pack<FO>((uint64_t)__double_as_longlong(acc[i][j][r]));
+                const uint64_t q = round_pack<FO, MODE>((uint64_t)__double_as_longlong(acc[i][j][r]));
                 uint64_t g[GO];
                 g[0] = q;
 #pragma unroll
@@ -178,7 +178,7 @@ __global__ void k_zero_rows(uint8_t* __restrict__ C, int64_t row_bytes, int64_t 
         C[(i / row_bytes) * pitch + i % row_bytes] = 0;
 }
 
-template <int KIN>
+template <int KIN, int MODE>
 static fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                             int64_t ldc, int M, int N, int K, hipStream_t stream)
 {
@@ -186,13 +186,13 @@ static fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t ld
     auto b = static_cast<const uint8_t*>(B);
     auto c = static_cast<uint8_t*>(C);
     switch (kout) {
-        case 2: k_gemm_f64<KIN, 2><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 3: k_gemm_f64<KIN, 3><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 4: k_gemm_f64<KIN, 4><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 5: k_gemm_f64<KIN, 5><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 6: k_gemm_f64<KIN, 6><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 7: k_gemm_f64<KIN, 7><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        default: k_gemm_f64<KIN, 8><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 2: k_gemm_f64<KIN, 2, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 3: k_gemm_f64<KIN, 3, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 4: k_gemm_f64<KIN, 4, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 5: k_gemm_f64<KIN, 5, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 6: k_gemm_f64<KIN, 6, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 7: k_gemm_f64<KIN, 7, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        default: k_gemm_f64<KIN, 8, 0><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
     }
     return check_launch("fb_gemm");
 }
@@ -231,6 +231,10 @@ extern "C" fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M
     const int64_t blocks = (M / GD_BM) * (N / GD_BN);
     if (blocks > INT32_MAX || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
         return set_error(FB_ERR_ARG, "fb_gemm: sizes too large");
-    if (fa.k == 5) return launch_f64<5>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
-    return launch_f64<6>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
+    return dispatch_round(fc, [&](auto rt) {
+        constexpr int MODE = decltype(rt)::value;
+        if (fa.k == 5)
+            return launch_f64<5, MODE>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
+        return launch_f64<6, MODE>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
+    });
 }

@@ -27,12 +27,16 @@ class FlyteError(RuntimeError):
         self.status = status
 
 
+ROUND_NEAREST_EVEN, ROUND_TOWARD_ZERO, ROUND_TO_ODD = 0, 1, 2
+
+
 class fb_format(ctypes.Structure):
-    _fields_ = [("base", ctypes.c_uint8), ("k", ctypes.c_uint8)]
+    _fields_ = [("base", ctypes.c_uint8), ("k", ctypes.c_uint8), ("round", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8)]
 
 
 class fb_gemv_desc(ctypes.Structure):
-    _fields_ = [("f", fb_format), ("reserved0", ctypes.c_uint16), ("m", ctypes.c_int32),
+    _fields_ = [("f", fb_format), ("m", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("reserved1", ctypes.c_int32), ("lda", ctypes.c_int64),
                 ("A", ctypes.c_void_p), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
 
@@ -48,6 +52,8 @@ _SIGS = {
     "fb_unpack": (_I32, [fb_format, _P, _P, _SZ, _P]),
     "fb_dot": (_I32, [fb_format, _SZ, _P, _P, _P, _P]),
     "fb_axpy": (_I32, [fb_format, _SZ, _DBL, _P, _P, _P]),
+    "fb_scale": (_I32, [fb_format, _SZ, _DBL, _P, _P]),
+    "fb_nrm2": (_I32, [fb_format, _SZ, _P, _P, _P]),
     "fb_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _P]),
     "fb_gemv_config": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, _P]),
     "fb_gemv_num_configs": (_I32, []),
@@ -110,9 +116,12 @@ def _check(status: int) -> None:
         raise FlyteError(status, last_error())
 
 
-def fmt(base_k) -> fb_format:
-    base, k = base_k
-    return fb_format(base, k)
+def fmt(f) -> fb_format:
+    """(base, k) or (base, k, round) -> fb_format."""
+    if isinstance(f, fb_format):
+        return f
+    base, k = f[0], f[1]
+    return fb_format(base, k, f[2] if len(f) > 2 else 0, 0)
 
 
 def native_dtype(base: int) -> torch.dtype:
@@ -131,8 +140,9 @@ def _ptr(t: torch.Tensor | None) -> int | None:
 
 # ---------------------------------------------------------------- codec
 def pack(f, src: torch.Tensor, out: torch.Tensor | None = None, n: int | None = None, stream=None):
-    """Rounds native values (float32 for base 32, float64 for base 64) to k-byte elements."""
-    base, k = f
+    """Rounds native values (float32 for base 32, float64 for base 64) to k-byte elements
+    (f = (base, k) or (base, k, round))."""
+    base, k = f[0], f[1]
     n = src.numel() if n is None else n
     if out is None:
         out = torch.empty(n * k, dtype=torch.uint8, device=src.device)
@@ -141,7 +151,7 @@ def pack(f, src: torch.Tensor, out: torch.Tensor | None = None, n: int | None = 
 
 
 def unpack(f, packed: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None, stream=None):
-    base, k = f
+    base, k = f[0], f[1]
     n = packed.numel() // k if n is None else n
     if out is None:
         out = torch.empty(n, dtype=native_dtype(base), device=packed.device)
@@ -151,7 +161,7 @@ def unpack(f, packed: torch.Tensor, n: int | None = None, out: torch.Tensor | No
 
 # ---------------------------------------------------------------- BLAS 1
 def dot(f, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None, stream=None):
-    base, k = f
+    base, k = f[0], f[1]
     n = x.numel() // k if n is None else n
     if out is None:
         out = torch.empty((), dtype=native_dtype(base), device=x.device)
@@ -161,16 +171,34 @@ def dot(f, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Te
 
 def axpy(f, alpha: float, x: torch.Tensor, y: torch.Tensor, n: int | None = None, stream=None):
     """y <- pack(alpha * x + y), in place on the packed tensor y."""
-    base, k = f
+    base, k = f[0], f[1]
     n = y.numel() // k if n is None else n
     _check(load().fb_axpy(fmt(f), n, float(alpha), _ptr(x), _ptr(y), _stream(stream)))
     return y
 
 
+def scale(f, alpha: float, x: torch.Tensor, n: int | None = None, stream=None):
+    """x <- pack(alpha * x), in place on the packed tensor x."""
+    base, k = f[0], f[1]
+    n = x.numel() // k if n is None else n
+    _check(load().fb_scale(fmt(f), n, float(alpha), _ptr(x), _stream(stream)))
+    return x
+
+
+def nrm2(f, x: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None, stream=None):
+    """sqrt(sum x_i^2) of a packed vector, as a 0-d native tensor on the device."""
+    base, k = f[0], f[1]
+    n = x.numel() // k if n is None else n
+    if out is None:
+        out = torch.empty((), dtype=native_dtype(base), device=x.device)
+    _check(load().fb_nrm2(fmt(f), n, _ptr(x), _ptr(out), _stream(stream)))
+    return out
+
+
 # ---------------------------------------------------------------- BLAS 2
 def gemv(f, A: torch.Tensor, m: int, n: int, x: torch.Tensor, y: torch.Tensor | None = None,
          lda: int | None = None, config: int | None = None, stream=None):
-    base, k = f
+    base, k = f[0], f[1]
     lda = n if lda is None else lda
     if y is None:
         y = torch.empty(m, dtype=native_dtype(base), device=A.device)
@@ -239,7 +267,7 @@ class BatchedGemv:
         self.items = items               # keeps the tensors alive
         arr = (fb_gemv_desc * max(1, len(items)))()
         for i, it in enumerate(items):
-            arr[i] = fb_gemv_desc(fmt(it.f), 0, it.m, it.n, 0, it.lda, _ptr(it.A), _ptr(it.x), _ptr(it.y))
+            arr[i] = fb_gemv_desc(fmt(it.f), it.m, it.n, 0, it.lda, _ptr(it.A), _ptr(it.x), _ptr(it.y))
         plan = _P()
         _check(load().fb_gemv_batched_plan(arr, len(items), ctypes.byref(plan)))
         self._plan = plan

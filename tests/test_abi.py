@@ -55,8 +55,11 @@ FAKE = 0x10000          # never dereferenced: validation fails first
 MISALIGNED = 0x10002
 
 
+def F(base, k, rnd=0, reserved=0):
+    return flyte.fb_format(base, k, rnd, reserved)
+
+
 def test_codec_argument_errors(lib):
-    F = flyte.fb_format
     assert st(lib.fb_pack(F(32, 5), FAKE, FAKE, 10, None))[0] == flyte.FB_ERR_FORMAT
     assert st(lib.fb_pack(F(64, 1), FAKE, FAKE, 10, None))[0] == flyte.FB_ERR_FORMAT
     assert st(lib.fb_unpack(F(16, 2), FAKE, FAKE, 10, None))[0] == flyte.FB_ERR_FORMAT
@@ -66,13 +69,17 @@ def test_codec_argument_errors(lib):
     assert lib.fb_axpy(F(64, 3), 10, 1.0, FAKE, MISALIGNED, None) == flyte.FB_ERR_ALIGN
     assert lib.fb_dot(F(64, 3), 10, FAKE, FAKE, None, None) == flyte.FB_ERR_ARG
     assert lib.fb_dot(F(64, 3), 10, FAKE, FAKE, MISALIGNED, None) == flyte.FB_ERR_ALIGN
+    assert lib.fb_pack(F(64, 5, 3), FAKE, FAKE, 10, None) == flyte.FB_ERR_FORMAT       # bad rounding mode
+    assert lib.fb_pack(F(64, 5, 0, 1), FAKE, FAKE, 10, None) == flyte.FB_ERR_FORMAT    # reserved set
+    assert lib.fb_scale(F(64, 5), 10, 2.0, MISALIGNED, None) == flyte.FB_ERR_ALIGN
+    assert lib.fb_nrm2(F(64, 5), 10, FAKE, None, None) == flyte.FB_ERR_ARG
+    assert lib.fb_scale(F(32, 2, 2), 0, 2.0, None, None) == flyte.FB_OK
     # n = 0 is valid and launches nothing (null data pointers allowed)
     assert lib.fb_pack(F(64, 5), None, None, 0, None) == flyte.FB_OK
     assert lib.fb_axpy(F(32, 3), 0, 2.0, None, None, None) == flyte.FB_OK
 
 
 def test_gemv_argument_errors(lib):
-    F = flyte.fb_format
     assert lib.fb_gemv(F(64, 9), 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
     assert lib.fb_gemv(F(64, 5), -1, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_ARG
     assert lib.fb_gemv(F(64, 5), 4, 8, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_ARG        # lda < n
@@ -84,7 +91,6 @@ def test_gemv_argument_errors(lib):
 
 
 def test_gemm_argument_errors(lib):
-    F = flyte.fb_format
     args = (128, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128, None)
     assert lib.fb_gemm(F(32, 2), F(32, 3), F(32, 4), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(64, 7), F(64, 7), F(64, 7), *args) == flyte.FB_ERR_UNSUPPORTED
@@ -105,8 +111,8 @@ def test_gemm_argument_errors(lib):
 def test_batched_plan_rejects_bad_descriptor(lib):
     D = flyte.fb_gemv_desc
     arr = (D * 2)()
-    arr[0] = D(flyte.fb_format(64, 5), 0, 4, 4, 0, 4, FAKE, FAKE, FAKE)
-    arr[1] = D(flyte.fb_format(64, 5), 0, 4, 4, 0, 3, FAKE, FAKE, FAKE)   # lda < n
+    arr[0] = D(flyte.fmt((64, 5)), 4, 4, 0, 4, FAKE, FAKE, FAKE)
+    arr[1] = D(flyte.fmt((64, 5)), 4, 4, 0, 3, FAKE, FAKE, FAKE)   # lda < n
     plan = ctypes.c_void_p()
     code = lib.fb_gemv_batched_plan(arr, 2, ctypes.byref(plan))
     assert code == flyte.FB_ERR_ARG and "descriptor 1" in flyte.last_error()
