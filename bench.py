@@ -316,7 +316,8 @@ def cpu_baseline(A, x, np):
 def bench_blas1(flyte, workloads, torch, dev, stream):
     """Streaming codec and BLAS-1 kernels on n = 2^28 elements (the 2 GiB FP64 side
     and every packed array exceed the 256 MB last-level cache): algorithmic GB/s and
-    fraction of 8 TB/s.  pack: n(W+k) bytes, unpack: n(k+W), axpy: 3nk, dot: 2nk."""
+    fraction of 8 TB/s.  pack: n(W+k) bytes, unpack: n(k+W), axpy: 3nk, dot: 2nk,
+    scale (in place): 2nk, nrm2: nk."""
     n = 1 << 28
     g = torch.Generator(device=dev)
     g.manual_seed(workloads.SEED_BASE + 1)
@@ -339,7 +340,8 @@ def bench_blas1(flyte, workloads, torch, dev, stream):
         return {"GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBPS, 4)}
 
     back = torch.empty_like(nat)
-    res = {"pack": {}, "unpack": {}, "axpy": {}, "dot": {}}
+    res = {"pack": {}, "unpack": {}, "axpy": {}, "dot": {}, "scale": {}, "nrm2": {},
+           "pack_toward_zero": {}, "pack_to_odd": {}}
     for k in range(2, 9):
         x = flyte.pack((64, k), nat)
         res["pack"][k] = rate(n * (8 + k), timed(lambda: flyte.pack((64, k), nat, out=x)))
@@ -349,6 +351,11 @@ def bench_blas1(flyte, workloads, torch, dev, stream):
             res["axpy"][k] = rate(3 * n * k, timed(lambda: flyte.axpy((64, k), 1.0 / 3.0, x, y)))
             r = torch.empty((), dtype=torch.float64, device=dev)
             res["dot"][k] = rate(2 * n * k, timed(lambda: flyte.dot((64, k), x, y, out=r)))
+            res["scale"][k] = rate(2 * n * k, timed(lambda: flyte.scale((64, k), 1.0 + 2.0 ** -40, y)))
+            res["nrm2"][k] = rate(n * k, timed(lambda: flyte.nrm2((64, k), x, out=r)))
+            if k in (3, 5):
+                res["pack_toward_zero"][k] = rate(n * (8 + k), timed(lambda: flyte.pack((64, k, 1), nat, out=x)))
+                res["pack_to_odd"][k] = rate(n * (8 + k), timed(lambda: flyte.pack((64, k, 2), nat, out=x)))
             del y
         del x
     del nat, back

@@ -43,8 +43,10 @@
  *    the calling thread are in fb_last_error().
  *  - n = 0 (or m = 0) is valid and launches nothing (fb_dot writes 0).
  *  - Nothing aborts, throws or prints.  Hot calls allocate no device memory,
- *    except fb_dot's per-(device, stream) partial-sum buffer (16 KiB), which
- *    is allocated on the first fb_dot call on that stream and kept.
+ *    except a per-(device, stream) workspace for partial sums (fb_dot,
+ *    fb_dot_packed, fb_nrm2: 16 KiB; transposed fb_gemv_ex: slabs * n native
+ *    values), allocated on first use on that stream and kept; growing it
+ *    synchronises the stream.
  *  - Input and output ranges must not overlap unless a call says so.
  */
 #ifndef FLYTE_H
@@ -106,6 +108,11 @@ fb_status fb_unpack(fb_format f, const void *src_packed, void *dst_native, size_
 fb_status fb_dot(fb_format f, size_t n, const void *x, const void *y, void *result,
                  hipStream_t stream);
 
+/* fb_dot with the result stored in format fr (same base as f): the base-type
+ * sum rounded once in fr's rounding mode, fr.k bytes in device memory. */
+fb_status fb_dot_packed(fb_format f, fb_format fr, size_t n, const void *x, const void *y,
+                        void *result, hipStream_t stream);
+
 /* y_i <- pack(fma(alpha, unpack(x_i), unpack(y_i))), in place on y.
  * alpha is first rounded to the native type.  Bit-exact per element.
  * x and y are packed (n*k bytes); x must not overlap y. */
@@ -131,6 +138,17 @@ fb_status fb_nrm2(fb_format f, size_t n, const void *x, void *result, hipStream_
  * autotuner cache, else a default for the shape). */
 fb_status fb_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
                   const void *x, void *y, hipStream_t stream);
+
+/* y = op(A) x with y stored in format fy (same base as fa; fy with k bytes =
+ * the base width means a native y; otherwise each y element is the base-type
+ * result rounded once to fy in fy's rounding mode).  trans = 0: y (m
+ * elements) = A x, x has n values, same kernels and order as fb_gemv.
+ * trans = 1: y (n elements) = A^T x, x has m values: each y_j is a fixed
+ * sequence of fmas over slabs of rows plus a fixed-order sum of the slab
+ * results (kept in the per-stream workspace, which grows to slabs * n native
+ * values and then stays allocated; growing it synchronises the stream). */
+fb_status fb_gemv_ex(fb_format fa, fb_format fy, int32_t trans, int64_t m, int64_t n, const void *A,
+                     int64_t lda, const void *x, void *y, hipStream_t stream);
 
 /* Same as fb_gemv with the tile configuration forced: config is an index in
  * [0, fb_gemv_num_configs()).  Used by the autotuner and for reproducibility. */

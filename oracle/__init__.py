@@ -78,6 +78,8 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "fbo_scale": (None, [c_int, c_int, c_int, c_sz, c_dbl, c_p]),
         "fbo_nrm2_naive": (c_dbl, [c_int, c_int, c_sz, c_p]),
         "fbo_nrm2_exact": (c_dbl, [c_int, c_int, c_sz, c_p]),
+        "fbo_gemv_t_naive": (None, [c_int, c_int, c_i64, c_i64, c_p, c_i64, c_p, c_p]),
+        "fbo_gemv_t_exact": (None, [c_int, c_int, c_i64, c_i64, c_p, c_i64, c_p, c_p, c_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -237,6 +239,24 @@ class Oracle:
             aa = np.empty(1, dtype=np.float64)
             self.lib.fbo_gemv_exact(base, k, 1, n, _ptr(seg), lda, _ptr(x), _ptr(yy), _ptr(aa))
             y[t], ab[t] = yy[0], aa[0]
+        return y, ab
+
+    def gemv_t_naive(self, base: int, k: int, m: int, n: int, A: np.ndarray, lda: int,
+                     x: np.ndarray) -> np.ndarray:
+        """y = A^T x, sequential fma over rows per column."""
+        A = np.ascontiguousarray(A, dtype=np.uint8).reshape(-1)
+        x = np.ascontiguousarray(x, dtype=_native_dtype(base))
+        y = np.empty(n, dtype=_native_dtype(base))
+        self.lib.fbo_gemv_t_naive(base, k, m, n, _ptr(A), lda, _ptr(x), _ptr(y))
+        return y
+
+    def gemv_t_exact(self, base: int, k: int, m: int, n: int, A: np.ndarray, lda: int, x: np.ndarray):
+        """Exact y = A^T x (rounded once to the base type, as float64) and sum_i |A_ij x_i|."""
+        A = np.ascontiguousarray(A, dtype=np.uint8).reshape(-1)
+        x = np.ascontiguousarray(x, dtype=_native_dtype(base))
+        y = np.empty(n, dtype=np.float64)
+        ab = np.empty(n, dtype=np.float64)
+        self.lib.fbo_gemv_t_exact(base, k, m, n, _ptr(A), lda, _ptr(x), _ptr(y), _ptr(ab))
         return y, ab
 
     def gemm_entries(self, fa, fb, K: int, A: np.ndarray, lda: int, B: np.ndarray, ldb: int,

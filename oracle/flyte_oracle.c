@@ -541,6 +541,48 @@ void fbo_gemv_exact(int base, int k, int64_t m, int64_t n, const uint8_t *A, int
     }
 }
 
+/* Transposed GEMV y = A^T x: A is m x n row-major (lda), x has m native
+ * values, y has n.  naive: for each column, a sequential fma over the rows in
+ * increasing order; exact: per column the long-accumulator sum rounded once
+ * (returned as double), and sum_i |A_ij x_i|. */
+void fbo_gemv_t_naive(int base, int k, int64_t m, int64_t n, const uint8_t *A, int64_t lda,
+                      const void *x, void *y)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        if (base == 32) {
+            float s = 0.0f;
+            for (int64_t r = 0; r < m; ++r)
+                s = fmaf((float)elem_value(base, k, A + (size_t)r * (size_t)lda * (size_t)k, (size_t)c),
+                         (float)native_at(x, base, (size_t)r), s);
+            native_set(y, base, (size_t)c, (double)s);
+        } else {
+            double s = 0.0;
+            for (int64_t r = 0; r < m; ++r)
+                s = fma(elem_value(base, k, A + (size_t)r * (size_t)lda * (size_t)k, (size_t)c),
+                        native_at(x, base, (size_t)r), s);
+            native_set(y, base, (size_t)c, s);
+        }
+    }
+}
+
+void fbo_gemv_t_exact(int base, int k, int64_t m, int64_t n, const uint8_t *A, int64_t lda,
+                      const void *x, double *y_exact, double *abscol)
+{
+    for (int64_t c = 0; c < n; ++c) {
+        longacc a, b;
+        acc_init(&a);
+        acc_init(&b);
+        for (int64_t r = 0; r < m; ++r) {
+            double av = elem_value(base, k, A + (size_t)r * (size_t)lda * (size_t)k, (size_t)c);
+            double xv = native_at(x, base, (size_t)r);
+            acc_add_product(&a, av, xv);
+            if (abscol) acc_add_product(&b, fabs(av), fabs(xv));
+        }
+        y_exact[c] = base == 32 ? (double)(float)acc_round(&a, 24, -126, 127) : acc_round(&a, 53, -1022, 1023);
+        if (abscol) abscol[c] = acc_round(&b, 53, -1022, 1023);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* GEMM C = A B.  A is M x K (lda), B is K x N (ldb), row-major, packed */
 /* in formats fa, fb.  For each requested entry (i, j) the exact dot of  */

@@ -29,8 +29,6 @@ namespace flyte {
 
 fb_status gemv_validate(const char* what, fb_format f, int64_t m, int64_t n, const void* A, int64_t lda,
                         const void* x, const void* y);
-fb_status gemv_launch_tile(fb_format f, int64_t m, int64_t n, const void* A, int64_t lda, const void* x, void* y,
-                           int tile, hipStream_t stream);
 int tune_lookup(fb_format f, int64_t m, int64_t n);
 void tune_store(fb_format f, int64_t m, int64_t n, int tile, double us);
 const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks);
@@ -203,7 +201,7 @@ static fb_status build_tables(const std::vector<fb_gemv_desc>& descs, const std:
         const fb_gemv_desc& d = descs[i];
         const int tile = tiles[i];
         const TileInfo ti = gemv_tile_info(tile);
-        dd[i].a = GemvArgs{static_cast<const uint8_t*>(d.A), d.lda * d.f.k, d.x, d.y, d.m, d.n};
+        dd[i].a = GemvArgs{static_cast<const uint8_t*>(d.A), d.lda * d.f.k, d.x, d.y, d.m, d.n, 0, 0};
         dd[i].code = format_index(d.f) * kBatchedNumTiles + batched_slot(tile);
         dd[i].pad = 0;
         if (d.m == 0) continue;
@@ -442,7 +440,7 @@ extern "C" fb_status fb_gemv_batched_loop_graph(fb_plan* plan, hipStream_t strea
         for (size_t i = 0; i < plan->descs.size() && ok; ++i) {
             const fb_gemv_desc& d = plan->descs[i];
             if (d.m == 0) continue;
-            GemvArgs a{static_cast<const uint8_t*>(d.A), d.lda * d.f.k, d.x, d.y, d.m, d.n};
+            GemvArgs a{static_cast<const uint8_t*>(d.A), d.lda * d.f.k, d.x, d.y, d.m, d.n, 0, 0};
             unsigned blocks = 0;
             const void* fn = gemv_kernel_fn(d.f, plan->tiles[i], d.m, &blocks);
             void* args[] = {&a};

@@ -7,9 +7,6 @@
 // U of them per loop trip, so each wave-wide memory instruction touches one
 // contiguous span.  The fewer than UNIT elements after the last whole unit are
 // handled one by one with byte accesses by the first threads of block 0.
-#include <mutex>
-#include <map>
-
 #include "codec.hpp"
 #include "common.hpp"
 
@@ -274,6 +271,19 @@ __global__ void k_store_zero(N* out)
     *out = N(0);
 }
 
+// Sum of the partials in a fixed order, rounded once to a packed result.
+template <class F>
+__global__ void __launch_bounds__(kBlock)
+k_dot_final_packed(const typename F::native_t* __restrict__ partials, int nparts, uint8_t* __restrict__ out, int rk,
+                   int rmode)
+{
+    using N = typename F::native_t;
+    N acc = N(0);
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc = acc + partials[i];
+    const N s = block_sum(acc);
+    if (threadIdx.x == 0) store_bytes_rt(out, pack_runtime((uint64_t)as_bits<F>(s), F::base, rk, rmode), rk);
+}
+
 // ---------------------------------------------------------------- host side
 constexpr int kMaxDotBlocks = 2048;
 
@@ -287,27 +297,10 @@ static int stream_grid(int64_t nunits, int unroll)
     return (int)blocks;
 }
 
-// Partial-sum buffer for fb_dot, one per (device, stream), kept for the life
-// of the process.
+// Partial sums of fb_dot / fb_nrm2 live in the per-stream workspace.
 static fb_status dot_workspace(hipStream_t stream, void** out)
 {
-    static std::mutex mu;
-    static std::map<std::pair<int, hipStream_t>, void*> cache;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return set_error(FB_ERR_RUNTIME, "fb_dot: hipGetDevice failed");
-    std::lock_guard<std::mutex> lk(mu);
-    auto key = std::make_pair(dev, stream);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-        *out = it->second;
-        return FB_OK;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, kMaxDotBlocks * sizeof(double)) != hipSuccess)
-        return set_error(FB_ERR_RUNTIME, "fb_dot: workspace allocation failed");
-    cache[key] = p;
-    *out = p;
-    return FB_OK;
+    return stream_workspace(stream, kMaxDotBlocks * sizeof(double), out);
 }
 
 static fb_status check_vec(const char* what, fb_format f, const void* a, const void* b, size_t n)
@@ -392,6 +385,33 @@ extern "C" fb_status fb_dot(fb_format f, size_t n, const void* x, const void* y,
                                                                (int64_t)n, static_cast<N*>(ws));
         k_dot_final<N, false><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
         return check_launch("fb_dot");
+    });
+}
+
+extern "C" fb_status fb_dot_packed(fb_format f, fb_format fr, size_t n, const void* x, const void* y, void* result,
+                                   hipStream_t stream)
+{
+    if (!result) return set_error(FB_ERR_ARG, "fb_dot_packed: null result");
+    if (!format_ok(fr) || fr.base != f.base)
+        return set_error(FB_ERR_FORMAT, "fb_dot_packed: result format must be a valid format of the same base");
+    fb_status st = check_vec("fb_dot_packed", f, x, y, n);
+    if (st != FB_OK) return st;
+    return dispatch_format(f, [&](auto tag) {
+        using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
+        using N = typename F::native_t;
+        void* ws = nullptr;
+        fb_status s2 = dot_workspace(stream, &ws);
+        if (s2 != FB_OK) return s2;
+        const int64_t nunits = (int64_t)(n / F::UNIT);
+        int grid = n ? stream_grid(nunits, kUnroll) : 0;
+        if (grid > kMaxDotBlocks) grid = kMaxDotBlocks;
+        if (grid > 0)
+            k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
+                                                                   static_cast<const uint32_t*>(y), nunits,
+                                                                   (int64_t)n, static_cast<N*>(ws));
+        k_dot_final_packed<F><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<uint8_t*>(result),
+                                                        fr.k, fr.round);
+        return check_launch("fb_dot_packed");
     });
 }
 

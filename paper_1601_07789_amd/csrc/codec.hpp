@@ -197,6 +197,31 @@ __device__ __forceinline__ typename F::bits_t round_pack(typename F::bits_t u)
     }
 }
 
+// Pack with the format given at run time (base width W = 32 or 64, k bytes,
+// rounding mode): the same rules as round_pack, with runtime shift amounts.
+// Used where one value is packed per result (GEMV/dot outputs), so the cost
+// of variable shifts does not matter.
+__device__ __forceinline__ uint64_t pack_runtime(uint64_t u, int W, int k, int mode)
+{
+    const int E = W == 32 ? 8 : 11;
+    const int D = W - 8 * k;
+    if (D == 0) return u;
+    const int M = 8 * k - 1 - E;
+    const uint64_t one = 1;
+    const uint64_t abs_mask = (W == 64) ? ~(one << 63) : ((one << 31) - 1);
+    const uint64_t inf_bits = ((one << E) - 1) << (W - 1 - E);
+    const uint64_t q = u >> D;
+    if ((u & abs_mask) > inf_bits) return ((q & ((one << M) - 1)) == 0) ? (q | (one << (M - 1))) : q;
+    if (mode == 0) return (u + ((one << (D - 1)) - 1) + (q & one)) >> D;
+    if (mode == 2) return q | (uint64_t)((u & ((one << D) - 1)) != 0);
+    return q;
+}
+
+__device__ __forceinline__ void store_bytes_rt(uint8_t* p, uint64_t q, int k)
+{
+    for (int j = 0; j < k; ++j) p[j] = uint8_t(q >> (8 * j));
+}
+
 // Stream byte that holds byte bi of packed element e, when the packed values
 // sit one per native word (low k bytes of a 4- or 8-byte word).
 template <class F>

@@ -73,4 +73,18 @@ auto dispatch_format(fb_format f, Fn&& fn)
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
+// Device scratch of at least `bytes` for calls on `stream` (one buffer per
+// device and stream, kept for the life of the process).  Growing it first
+// synchronises the stream, so no earlier call on it still uses the old buffer.
+fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out);
+
+// One GEMV launch with a given tile (yk = 0: native y; else y packed in yk
+// bytes with rounding mode ymode).
+fb_status gemv_launch_tile(fb_format f, int64_t m, int64_t n, const void* A, int64_t lda, const void* x, void* y,
+                           int tile, hipStream_t stream, int yk = 0, int ymode = 0);
+
+// Transposed GEMV y = A^T x with y native or packed in fy (arguments validated).
+fb_status gemv_t_launch(fb_format fa, fb_format fy, int64_t m, int64_t n, const void* A, int64_t lda, const void* x,
+                        void* y, hipStream_t stream);
+
 }  // namespace flyte

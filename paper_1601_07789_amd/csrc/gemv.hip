@@ -74,9 +74,9 @@ fb_status gemv_validate(const char* what, fb_format f, int64_t m, int64_t n, con
 }
 
 fb_status gemv_launch_tile(fb_format f, int64_t m, int64_t n, const void* A, int64_t lda, const void* x, void* y,
-                           int tile, hipStream_t stream)
+                           int tile, hipStream_t stream, int yk, int ymode)
 {
-    GemvArgs a{static_cast<const uint8_t*>(A), lda * f.k, x, y, (int32_t)m, (int32_t)n};
+    GemvArgs a{static_cast<const uint8_t*>(A), lda * f.k, x, y, (int32_t)m, (int32_t)n, yk, ymode};
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         return launch_gemv<F>(a, tile, stream);
@@ -156,6 +156,20 @@ extern "C" fb_status fb_gemv(fb_format f, int64_t m, int64_t n, const void* A, i
     fb_status st = gemv_validate("fb_gemv", f, m, n, A, lda, x, y);
     if (st != FB_OK || m == 0) return st;
     return gemv_launch_tile(f, m, n, A, lda, x, y, gemv_pick_tile(f, m, n), stream);
+}
+
+extern "C" fb_status fb_gemv_ex(fb_format fa, fb_format fy, int32_t trans, int64_t m, int64_t n, const void* A,
+                                int64_t lda, const void* x, void* y, hipStream_t stream)
+{
+    fb_status st = gemv_validate("fb_gemv_ex", fa, m, n, A, lda, x, y);
+    if (st != FB_OK) return st;
+    if (!format_ok(fy) || fy.base != fa.base)
+        return set_error(FB_ERR_FORMAT, "fb_gemv_ex: y format must be a valid format of the same base");
+    if (trans != 0 && trans != 1) return set_error(FB_ERR_ARG, "fb_gemv_ex: trans must be 0 or 1");
+    if (trans == 1) return gemv_t_launch(fa, fy, m, n, A, lda, x, y, stream);
+    if (m == 0) return FB_OK;
+    const int yk = (fy.k * 8 == fy.base) ? 0 : fy.k;
+    return gemv_launch_tile(fa, m, n, A, lda, x, y, gemv_pick_tile(fa, m, n), stream, yk, fy.round);
 }
 
 extern "C" int32_t fb_tune_lookup(fb_format f, int64_t m, int64_t n)

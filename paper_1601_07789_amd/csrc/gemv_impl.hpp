@@ -27,8 +27,10 @@ struct GemvArgs {
     const uint8_t* A;      // packed matrix
     int64_t row_bytes;     // lda * k
     const void* x;         // native
-    void* y;               // native
+    void* y;               // native, or packed in yk bytes
     int32_t m, n;
+    int32_t yk;            // 0: y is native; else y is stored in yk bytes per element
+    int32_t ymode;         // rounding mode of a packed y
 };
 
 template <int LPR, int RPW, int U, int KS = 1, bool NT = false, bool STAGED = false>
@@ -212,10 +214,20 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
         __syncthreads();   // the block may run another tile (persistent kernel) and reuse part
     }
     if (ws == 0 && gl == 0) {
-        N* y = static_cast<N*>(a.y);
+        if (a.yk == 0) {
+            N* y = static_cast<N*>(a.y);
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
-            if (r0 + r < a.m) y[r0 + r] = acc[r];
+            for (int r = 0; r < RPW; ++r)
+                if (r0 + r < a.m) y[r0 + r] = acc[r];
+        } else {
+            // packed output: one rounding of the base-type result, byte stores
+            uint8_t* y = static_cast<uint8_t*>(a.y);
+#pragma unroll
+            for (int r = 0; r < RPW; ++r)
+                if (r0 + r < a.m)
+                    store_bytes_rt(y + (r0 + r) * a.yk,
+                                   pack_runtime((uint64_t)as_bits<F>(acc[r]), F::base, a.yk, a.ymode), a.yk);
+        }
     }
 }
 

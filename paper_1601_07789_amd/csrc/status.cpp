@@ -2,6 +2,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <map>
 #include <mutex>
 #include <unordered_map>
 
@@ -36,6 +37,30 @@ int device_cu_count()
         cus = 256;
     cache[dev] = cus;
     return cus;
+}
+
+fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(FB_ERR_RUNTIME, "workspace: hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(mu);
+    auto& slot = cache[std::make_pair(dev, stream)];
+    if (slot.second < bytes) {
+        size_t want = bytes < 2 * slot.second ? 2 * slot.second : bytes;
+        if (want < 16384) want = 16384;
+        if (slot.first) {
+            if (hipStreamSynchronize(stream) != hipSuccess || hipFree(slot.first) != hipSuccess)
+                return set_error(FB_ERR_RUNTIME, "workspace: could not release the previous buffer");
+            slot = {nullptr, 0};
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) return set_error(FB_ERR_RUNTIME, "workspace: allocation failed");
+        slot = {p, want};
+    }
+    *out = slot.first;
+    return FB_OK;
 }
 
 }  // namespace flyte

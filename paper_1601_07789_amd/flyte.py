@@ -56,6 +56,8 @@ _SIGS = {
     "fb_nrm2": (_I32, [fb_format, _SZ, _P, _P, _P]),
     "fb_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _P]),
     "fb_gemv_config": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, _P]),
+    "fb_gemv_ex": (_I32, [fb_format, fb_format, _I32, _I64, _I64, _P, _I64, _P, _P, _P]),
+    "fb_dot_packed": (_I32, [fb_format, fb_format, _SZ, _P, _P, _P, _P]),
     "fb_gemv_num_configs": (_I32, []),
     "fb_gemv_config_info": (_I32, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "fb_tune_gemv": (_I32, [fb_format, _I64, _I64, _P, _I64, _P, _P, _I32, ctypes.POINTER(_I32), _P]),
@@ -207,6 +209,32 @@ def gemv(f, A: torch.Tensor, m: int, n: int, x: torch.Tensor, y: torch.Tensor | 
     else:
         _check(load().fb_gemv_config(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), config, _stream(stream)))
     return y
+
+
+def gemv_ex(fa, fy, trans: bool, A: torch.Tensor, m: int, n: int, x: torch.Tensor,
+            y: torch.Tensor | None = None, lda: int | None = None, stream=None):
+    """y = A x (trans False, m outputs) or A^T x (trans True, n outputs), y in format fy."""
+    base = fa[0]
+    lda = n if lda is None else lda
+    ny = n if trans else m
+    if y is None:
+        if fy[1] * 8 == base:
+            y = torch.empty(ny, dtype=native_dtype(base), device=A.device)
+        else:
+            y = torch.empty(ny * fy[1], dtype=torch.uint8, device=A.device)
+    _check(load().fb_gemv_ex(fmt(fa), fmt(fy), 1 if trans else 0, m, n, _ptr(A), lda, _ptr(x), _ptr(y),
+                             _stream(stream)))
+    return y
+
+
+def dot_packed(f, fr, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Tensor | None = None,
+               stream=None):
+    """dot with the result packed in format fr: a uint8 tensor of fr.k bytes."""
+    n = x.numel() // f[1] if n is None else n
+    if out is None:
+        out = torch.empty(fr[1], dtype=torch.uint8, device=x.device)
+    _check(load().fb_dot_packed(fmt(f), fmt(fr), n, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
+    return out
 
 
 def gemv_num_configs() -> int:

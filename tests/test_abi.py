@@ -88,6 +88,10 @@ def test_gemv_argument_errors(lib):
     assert lib.fb_gemv(F(64, 5), 4, 4, None, 4, FAKE, FAKE, None) == flyte.FB_ERR_ARG
     assert lib.fb_gemv_config(F(64, 5), 4, 4, FAKE, 4, FAKE, FAKE, 99, None) == flyte.FB_ERR_ARG
     assert lib.fb_gemv(F(64, 5), 0, 4, None, 4, None, None, None) == flyte.FB_OK            # m = 0
+    assert lib.fb_gemv_ex(F(64, 5), F(32, 3), 0, 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
+    assert lib.fb_gemv_ex(F(64, 5), F(64, 3), 2, 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_ARG
+    assert lib.fb_gemv_ex(F(64, 5), F(64, 3, 3), 0, 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
+    assert lib.fb_dot_packed(F(64, 5), F(32, 2), 4, FAKE, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
 
 
 def test_gemm_argument_errors(lib):

@@ -196,6 +196,33 @@ def test_gemv_naive_integer_data(orc, base, k):
     assert np.array_equal(y, (Av[:, :n].astype(np.int64) @ xv.astype(np.int64)).astype(native_dtype(base)))
 
 
+@pytest.mark.parametrize("base,k", [(32, 3), (64, 5), (64, 8)])
+def test_gemv_t_exact_vs_rational(orc, base, k):
+    m, n, lda = 41, 9, 12
+    A = orc.pack(base, k, wide_values(m * lda, 500 + k, base))
+    x = wide_values(m, 600 + k, base)
+    y, ab = orc.gemv_t_exact(base, k, m, n, A, lda, x)
+    rowbytes = lda * k
+    xf = [vr.decode(base, int(u)) for u in x.view(bits_dtype(base))]
+    Af = [frac_of_packed(orc, base, k, A[r * rowbytes:r * rowbytes + n * k]) for r in range(m)]
+    for c in range(n):
+        terms = [Af[r][c] * xf[r] for r in range(m)]
+        assert y[c] == vr.to_float(vr.round_to_base(sum(terms, Fraction(0)), base))
+        assert ab[c] == float(sum((abs(t) for t in terms), Fraction(0)))
+
+
+def test_gemv_t_naive_integer_data_and_order(orc):
+    g = np.random.default_rng(12)
+    m, n = 37, 21
+    Av = g.integers(-100, 100, (m, n)).astype(np.float64)
+    xv = g.integers(-100, 100, m).astype(np.float64)
+    A = orc.pack(64, 6, Av.reshape(-1))
+    assert np.array_equal(orc.gemv_t_naive(64, 6, m, n, A, n, xv), Av.T @ xv)
+    # sequential over rows: the small middle term is lost, as in the dot closed form
+    A = orc.pack(64, 8, np.array([[1.0], [2.0 ** -60], [-1.0]]).reshape(-1))
+    assert orc.gemv_t_naive(64, 8, 3, 1, A, 1, np.ones(3))[0] == 0.0
+
+
 # ---------------------------------------------------------------- gemm
 def test_gemm_entries_vs_rational(orc):
     g = np.random.default_rng(3)
