@@ -179,6 +179,21 @@ def main() -> int:
         per_k[k]["speedup_vs_fp64_stored"] = round(fp64_stored_us / per_k[k]["us"], 3)
         per_k[k]["ideal_8_over_k"] = round(8.0 / k, 3)
 
+    # the transposed GEMV (y = A^T x) on the same matrices
+    trans = {}
+    for k in KS:
+        yt = torch.empty(N, dtype=torch.float64, device=dev)
+        for r in range(R[k]):
+            flyte.gemv_ex((64, k), (64, 8), True, A[k][r], M, N, x, y=yt)
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        for r in range(R[k]):
+            flyte.gemv_ex((64, k), (64, 8), True, A[k][r], M, N, x, y=yt)
+        e1.record(stream)
+        e1.synchronize()
+        us = 1000.0 * e0.elapsed_time(e1) / R[k]
+        trans[k] = {"us": round(us, 2), "GBps": round(gemv_bytes(k) / (us * 1e-6) / 1e9, 1)}
+
     # roofline over the GEMV launches (one kernel template, six formats)
     tot_bytes = sum(gemv_bytes(k) for k in KS)
     tot_us = sum(per_k[k]["us"] for k in KS)
@@ -199,7 +214,7 @@ def main() -> int:
         cpu = cpu_baseline(A, x, np)
 
     # ------------------------------------------------------------ GEMM (after the timed region)
-    detail = {"per_k": per_k, "vendor_fp64_gemv_us": round(vendor_us, 2), "rotate": R,
+    detail = {"per_k": per_k, "transposed_per_k": trans, "vendor_fp64_gemv_us": round(vendor_us, 2), "rotate": R,
               "bytes_per_step": bytes_per_step, "stream_reference": stream_ref,
               "gemv_frac_of_measured_read_stream": round(achieved / stream_ref["read_GBps"], 4)}
     del A
@@ -440,13 +455,13 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
     g = torch.Generator(device=dev)
     g.manual_seed(workloads.SEED_BASE + 2)
     Mg = 8192
-    for k, name in [(2, "bf16"), (3, "three_product")]:
+    for k, name, flags in [(2, "bf16", 0), (3, "three_product", 0), (3, "four_product", flyte.GEMM_FOUR_PRODUCTS)]:
         Av = torch.empty(Mg * Mg, dtype=torch.float32, device=dev).normal_(generator=g)
         Bv = torch.empty(Mg * Mg, dtype=torch.float32, device=dev).normal_(generator=g)
         Ap, Bp = flyte.pack((32, k), Av), flyte.pack((32, k), Bv)
         del Av, Bv
         C = torch.empty(Mg * Mg, dtype=torch.float32, device=dev)
-        ms = timed(lambda: flyte.gemm((32, k), (32, k), (32, 4), Mg, Mg, Mg, Ap, Bp, C), 10)
+        ms = timed(lambda: flyte.gemm((32, k), (32, k), (32, 4), Mg, Mg, Mg, Ap, Bp, C, flags=flags), 10)
         out[name] = {"M": Mg, "N": Mg, "K": Mg, "ms": round(ms, 3),
                      "TFLOPs": round(2.0 * Mg ** 3 / (ms * 1e-3) / 1e12, 1)}
         del Ap, Bp, C

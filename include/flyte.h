@@ -258,6 +258,18 @@ fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N
                   const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
                   hipStream_t stream);
 
+/* fb_gemm with options.  FB_GEMM_FOUR_PRODUCTS ({32,3} operands only): adds
+ * lo*lo to the three products, so every product of the split operands is
+ * exact and only the FP32 accumulation rounds.  Other flag bits: FB_ERR_ARG. */
+typedef enum fb_gemm_flags {
+    FB_GEMM_DEFAULT = 0,
+    FB_GEMM_FOUR_PRODUCTS = 1
+} fb_gemm_flags;
+
+fb_status fb_gemm_ex(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
+                     const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
+                     uint32_t flags, hipStream_t stream);
+
 /* ------------------------------------------------------------------ errors */
 
 const char *fb_status_str(fb_status status);

@@ -9,6 +9,8 @@
 //    exponent >= 9; rounded to nearest otherwise; 0 for Inf/NaN).  The tile
 //    product is hi*hi + hi*lo + lo*hi: three BF16 MFMAs per step into the same
 //    FP32 accumulators (lo*lo, below 2^-16 relative, is dropped).
+//  MODE 2 ({32,3}, four products): MODE 1 plus lo*lo, so every product of the
+//    split operands is formed exactly and only the FP32 accumulation rounds.
 //
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
@@ -256,6 +258,8 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl[j], acc[i][j], 0, 0, 0);
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], b[j], acc[i][j], 0, 0, 0);
+                        if constexpr (MODE == 2)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bl[j], acc[i][j], 0, 0, 0);
                     }
             }
         }
@@ -311,11 +315,16 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
             launch_b32<0, 256, 256, 64, 2, 4, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
         else
             launch_b32<0, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
-    } else {
+    } else if (mode == 1) {
         if (M % 256 == 0)
             launch_b32<1, 256, 128, 32, 2, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
         else
             launch_b32<1, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    } else {
+        if (M % 256 == 0)
+            launch_b32<2, 256, 128, 32, 2, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        else
+            launch_b32<2, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     }
     return check_launch("fb_gemm");
 }

@@ -201,9 +201,11 @@ static fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t ld
 
 using namespace flyte;
 
-extern "C" fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K, const void* A,
-                             int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t stream)
+extern "C" fb_status fb_gemm_ex(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
+                                const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc,
+                                uint32_t flags, hipStream_t stream)
 {
+    if (flags & ~(uint32_t)FB_GEMM_FOUR_PRODUCTS) return set_error(FB_ERR_ARG, "fb_gemm_ex: unknown flags");
     if (!format_ok(fa) || !format_ok(fb) || !format_ok(fc))
         return set_error(FB_ERR_FORMAT, "fb_gemm: invalid format");
     if (M < 0 || N < 0 || K < 0) return set_error(FB_ERR_ARG, "fb_gemm: negative size");
@@ -224,7 +226,11 @@ extern "C" fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M
         k_zero_rows<<<1024, 256, 0, stream>>>(static_cast<uint8_t*>(C), N * fc.k, ldc * fc.k, M);
         return check_launch("fb_gemm");
     }
-    if (bf16 || three) return gemm_bf16_launch(bf16 ? 0 : 1, M, N, K, A, lda, B, ldb, C, ldc, stream);
+    if ((flags & FB_GEMM_FOUR_PRODUCTS) && !three)
+        return set_error(FB_ERR_UNSUPPORTED, "fb_gemm_ex: four products apply to {32,3} operands only");
+    if (bf16 || three)
+        return gemm_bf16_launch(bf16 ? 0 : ((flags & FB_GEMM_FOUR_PRODUCTS) ? 2 : 1), M, N, K, A, lda, B, ldb, C, ldc,
+                                stream);
     if (M % GD_BM || N % GD_BN || K % GD_BK)
         return set_error(FB_ERR_UNSUPPORTED, "fb_gemm: binary64 paths need M, N multiples of %d and K of %d", GD_BM,
                          GD_BK);
@@ -237,4 +243,10 @@ extern "C" fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M
             return launch_f64<5, MODE>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
         return launch_f64<6, MODE>(fc.k, (unsigned)blocks, A, lda, B, ldb, C, ldc, (int)M, (int)N, (int)K, stream);
     });
+}
+
+extern "C" fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K, const void* A,
+                             int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t stream)
+{
+    return fb_gemm_ex(fa, fb, fc, M, N, K, A, lda, B, ldb, C, ldc, 0, stream);
 }

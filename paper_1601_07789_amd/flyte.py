@@ -75,6 +75,8 @@ _SIGS = {
     "fb_plan_config": (_I32, [_P, _I32]),
     "fb_plan_destroy": (None, [_P]),
     "fb_gemm": (_I32, [fb_format, fb_format, fb_format, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P]),
+    "fb_gemm_ex": (_I32, [fb_format, fb_format, fb_format, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64,
+                          ctypes.c_uint32, _P]),
     "fb_status_str": (ctypes.c_char_p, [_I32]),
     "fb_last_error": (ctypes.c_char_p, []),
 }
@@ -332,8 +334,11 @@ class BatchedGemv:
 
 
 # ---------------------------------------------------------------- BLAS 3
+GEMM_FOUR_PRODUCTS = 1
+
+
 def gemm(fa, fb, fc, M: int, N: int, K: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,
-         lda: int | None = None, ldb: int | None = None, ldc: int | None = None, stream=None):
+         lda: int | None = None, ldb: int | None = None, ldc: int | None = None, flags: int = 0, stream=None):
     lda = K if lda is None else lda
     ldb = N if ldb is None else ldb
     ldc = N if ldc is None else ldc
@@ -342,6 +347,6 @@ def gemm(fa, fb, fc, M: int, N: int, K: int, A: torch.Tensor, B: torch.Tensor, C
             C = torch.empty(M * ldc, dtype=native_dtype(fc[0]), device=A.device)
         else:
             C = torch.empty(M * ldc * fc[1], dtype=torch.uint8, device=A.device)
-    _check(load().fb_gemm(fmt(fa), fmt(fb), fmt(fc), M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
-                          _stream(stream)))
+    _check(load().fb_gemm_ex(fmt(fa), fmt(fb), fmt(fc), M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
+                             flags, _stream(stream)))
     return C

@@ -110,6 +110,8 @@ def test_gemm_argument_errors(lib):
                        None) == flyte.FB_ERR_ALIGN
     assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 0, 128, 64, None, 64, None, 128, None, 128,
                        None) == flyte.FB_OK
+    assert lib.fb_gemm_ex(F(32, 2), F(32, 2), F(32, 4), *args[:-1], 1, None) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm_ex(F(32, 3), F(32, 3), F(32, 4), *args[:-1], 4, None) == flyte.FB_ERR_ARG
 
 
 def test_batched_plan_rejects_bad_descriptor(lib):

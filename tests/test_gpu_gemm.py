@@ -42,12 +42,15 @@ def all_entries(M, N):
     return ii.reshape(-1), jj.reshape(-1)
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 @pytest.mark.parametrize("shape", [(256, 384, 320), (512, 512, 192), (128, 256, 64)])
 def test_gemm_binary32_small_all_entries(dev, orc, k, shape):
-    """Every entry; the shapes exercise the 256 x 256, 256 x 128 and 128 x 128 tile paths."""
+    """Every entry; the shapes exercise the 256 x 256, 256 x 128 and 128 x 128 tile paths.
+    k = 4 here means the 3-byte operands with the four-product option."""
     import torch
     log(f"gemm b32 k={k} {shape}")
+    four = k == 4
+    k = 3 if four else k
     M, N, K = shape
     g = np.random.default_rng(11 + k)
     Av = g.standard_normal((M, K)).astype(np.float32)
@@ -57,11 +60,15 @@ def test_gemm_binary32_small_all_entries(dev, orc, k, shape):
     Bv[:, 5] *= np.float32(2.0 ** -20)
     A, B = orc.pack(32, k, Av.reshape(-1)), orc.pack(32, k, Bv.reshape(-1))
     C = flyte.gemm((32, k), (32, k), (32, 4), M, N, K, torch.from_numpy(A).to(dev),
-                   torch.from_numpy(B).to(dev)).cpu().numpy().reshape(M, N).astype(np.float64)
+                   torch.from_numpy(B).to(dev), flags=flyte.GEMM_FOUR_PRODUCTS if four else 0)
+    C = C.cpu().numpy().reshape(M, N).astype(np.float64)
     ii, jj = all_entries(M, N)
     ce, cab = orc.gemm_entries((32, k), (32, k), K, A, K, B, N, ii, jj)
     e1 = np.max(np.abs(C.reshape(-1) - ce) / cab)
-    bound = gam(K, U32) if k == 2 else 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2
+    if four:
+        bound = gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2
+    else:
+        bound = gam(K, U32) if k == 2 else 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2
     assert e1 <= bound, (e1, bound)
     if k == 3:
         # the 3-product must be far more accurate than plain BF16 of the rounded inputs
@@ -121,11 +128,14 @@ def sampled(orc, fa, K, A, B, N, C, M, seed, count=256):
     return ii, jj, ce, cab
 
 
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [2, 3, 4])
 def test_gemm_binary32_benchmark_size_sampled(dev, orc, k):
-    """M = N = K = 8192, N(0,1) entries (the precision-GEMM workload): sampled entries."""
+    """M = N = K = 8192, N(0,1) entries (the precision-GEMM workload): sampled entries
+    (k = 4: 3-byte operands with four products)."""
     import torch
     log(f"gemm b32 k={k} 8192^3 sampled")
+    four = k == 4
+    k = 3 if four else k
     n = 8192
     g = torch.Generator(device=dev)
     g.manual_seed(workloads.SEED_BASE + 2)
@@ -134,13 +144,16 @@ def test_gemm_binary32_benchmark_size_sampled(dev, orc, k):
     v.normal_(generator=g)
     B = flyte.pack((32, k), v)
     del v
-    C = flyte.gemm((32, k), (32, k), (32, 4), n, n, n, A, B)
+    C = flyte.gemm((32, k), (32, k), (32, 4), n, n, n, A, B, flags=flyte.GEMM_FOUR_PRODUCTS if four else 0)
     torch.cuda.synchronize()
     Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
     ii, jj, ce, cab = sampled(orc, (32, k), n, Ah, Bh, n, None, n, 3)
     got = C.view(n, n)[torch.from_numpy(ii).to(dev), torch.from_numpy(jj).to(dev)].cpu().numpy().astype(np.float64)
     e1 = np.max(np.abs(got - ce) / cab)
-    bound = gam(n, U32) if k == 2 else 2.0 ** -14 + gam(3 * n, U32) * (1 + 2.0 ** -7) ** 2
+    if four:
+        bound = gam(4 * n, U32) * (1 + 2.0 ** -7) ** 2
+    else:
+        bound = gam(n, U32) if k == 2 else 2.0 ** -14 + gam(3 * n, U32) * (1 + 2.0 ** -7) ** 2
     log(f"  e1 = {e1:.3e} (bound {bound:.3e})")
     assert e1 <= bound
     del A, B, C
