@@ -467,7 +467,7 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
         del Ap, Bp, C
     g.manual_seed(workloads.SEED_BASE + 4)
     Mf = 16384
-    for k in (5, 6):
+    for k in (5, 6, 3):
         Av = torch.empty(Mf * Mf, dtype=torch.float64, device=dev).normal_(generator=g)
         Ap = flyte.pack((64, k), Av)
         Av.normal_(generator=g)

@@ -1,0 +1,207 @@
+// FP64 matrix-core GEMM on binary64-derived k-byte operands (k = 2..8), with
+// the result rounded to a k-byte format in the epilogue.
+//
+// C = A B: A M x K and B K x N row-major packed in one binary64 format; C M x N
+// row-major in any binary64 format.  Operands are unpacked (Section 3.2) while
+// they are copied into LDS as FP64; products and sums run on
+// v_mfma_f64_16x16x4_f64 in FP64; each C entry is then rounded once to the
+// output format (Section 5.2) -- the double rounding of Section 3.1 (FP64
+// accumulation, then the cut) is part of the method.  For k <= 4 (at most
+// 21 significant bits) every product is exact in FP64, so only the FP64 sums
+// and the final cut round; the 11-bit exponent of these formats is kept whole.
+//
+// Tiling: a 256-thread workgroup computes 128 x 128 of C, each wave a 64 x 64
+// quarter as 4 x 4 MFMA tiles; K moves in steps of 16 through double-buffered
+// LDS.  Both operand tiles are stored k-major (A transposed while unpacking)
+// with rows padded to 144 doubles, so the 16 lanes that share a k read 16
+// consecutive doubles and the two lane halves of a read hit disjoint banks.
+// Epilogue: lane l holds rows l/16 + 4r (r = 0..3), column l%16, of each
+// 16 x 16 tile (the FP64 instruction's output order); the G lanes
+// of one dword-aligned group of columns pass their packed values to the
+// group's first lane (cross-lane shuffles), which assembles them with
+// v_perm_b32 and writes whole dwords, so no two lanes write the same dword.
+#pragma once
+
+#include "codec.hpp"
+#include "common.hpp"
+
+namespace flyte {
+
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int GD_BM = 128, GD_BN = 128, GD_BK = 16, GD_THREADS = 256;
+constexpr int GD_ROW = GD_BM + 16;    // doubles per padded LDS row
+
+__device__ __forceinline__ void gemm_tile_coords_f64(int ntm, int ntn, int& tm, int& tn)
+{
+    const int nb = ntm * ntn;
+    int pid = blockIdx.x;
+    if (nb % 8 == 0) pid = (pid % 8) * (nb / 8) + pid / 8;
+    constexpr int GROUP = 8;
+    const int per_group = GROUP * ntn;
+    const int group = pid / per_group;
+    const int first_m = group * GROUP;
+    const int gsize = (ntm - first_m) < GROUP ? (ntm - first_m) : GROUP;
+    tm = first_m + (pid % per_group) % gsize;
+    tn = (pid % per_group) / gsize;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int KIN, int KOUT, int MODE>
+__global__ void __launch_bounds__(GD_THREADS, 2)
+k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
+           uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K)
+{
+    using FI = Fmt<64, KIN>;
+    using FO = Fmt<64, KOUT>;
+    constexpr int U = FI::UNIT;                     // elements per loaded unit
+    constexpr int A_UNITS = GD_BM * GD_BK / U / GD_THREADS;
+    constexpr int B_UNITS = GD_BK * GD_BN / U / GD_THREADS;
+    static_assert(A_UNITS >= 1 && B_UNITS >= 1, "tile too small for the unit");
+    __shared__ __attribute__((aligned(16))) double lds[2][2][GD_BK * GD_ROW];   // [stage][A^T, B][k][m or n]
+
+    const int ntm = M / GD_BM, ntn = N / GD_BN;
+    int tm, tn;
+    gemm_tile_coords_f64(ntm, ntn, tm, tn);
+    const int m0 = tm * GD_BM, n0 = tn * GD_BN;
+    const int t = threadIdx.x, lane = t % 64, wid = t / 64;
+    const int wm = wid / 2, wn = wid % 2;
+
+    uint32_t ra[A_UNITS][FI::UNIT_DW], rb[B_UNITS][FI::UNIT_DW];
+    constexpr int A_UPR = GD_BK / U;    // A units per row of the tile
+    constexpr int B_UPR = GD_BN / U;    // B units per row of the tile
+
+    auto load_tiles = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = t + GD_THREADS * i, row = u / A_UPR, uc = u % A_UPR;
+            load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + uc * U) * KIN), ra[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = t + GD_THREADS * i, row = u / B_UPR, uc = u % B_UPR;
+            load_dwords(reinterpret_cast<const uint32_t*>(B + ((int64_t)(k0 + row) * ldb + n0 + uc * U) * KIN), rb[i]);
+        }
+    };
+    auto store_tiles = [&](int s) {
+        double* At = lds[s][0];
+        double* Bs = lds[s][1];
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = t + GD_THREADS * i, row = u / A_UPR, uc = u % A_UPR;
+            uint64_t x[U];
+            unpack_elems<FI, U>(ra[i], x);
+#pragma unroll
+            for (int c = 0; c < U; ++c) At[(uc * U + c) * GD_ROW + row] = __longlong_as_double((long long)x[c]);
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = t + GD_THREADS * i, row = u / B_UPR, uc = u % B_UPR;
+            uint64_t x[U];
+            unpack_elems<FI, U>(rb[i], x);
+#pragma unroll
+            for (int c = 0; c < U; ++c) Bs[row * GD_ROW + uc * U + c] = __longlong_as_double((long long)x[c]);
+        }
+    };
+
+    f64x4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+
+    auto compute = [&](int s) {
+        const double* At = lds[s][0];
+        const double* Bs = lds[s][1];
+        const int c16 = lane % 16, kq = lane / 16;
+#pragma unroll
+        for (int ks = 0; ks < GD_BK / 4; ++ks) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = At[(ks * 4 + kq) * GD_ROW + wm * 64 + i * 16 + c16];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[(ks * 4 + kq) * GD_ROW + wn * 64 + j * 16 + c16];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+    };
+
+    // the last K step is peeled so the loop body has no branches
+    const int KT = K / GD_BK;
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    for (int kt = 0; kt < KT - 1; ++kt) {
+        const int s = kt & 1;
+        load_tiles((kt + 1) * GD_BK);
+        compute(s);
+        store_tiles(s ^ 1);
+        __syncthreads();
+    }
+    compute((KT - 1) & 1);
+
+    // ---- epilogue: round to the output format and store whole dword groups
+    constexpr int GO = FO::G;
+    const int c16 = lane % 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + i * 16 + lane / 16 + 4 * r;
+                const int col = n0 + wn * 64 + j * 16 + c16;
+                const uint64_t q = round_pack<FO, MODE>((uint64_t)__double_as_longlong(acc[i][j][r]));
+                uint64_t g[GO];
+                g[0] = q;
+#pragma unroll
+                for (int e = 1; e < GO; ++e) g[e] = shfl_u64(q, (lane + e) % 64);
+                if (c16 % GO == 0) {
+                    uint32_t out[GO * KOUT / 4];
+                    assemble_elems<FO, GO>(g, out);
+                    store_dwords(reinterpret_cast<uint32_t*>(C + ((int64_t)row * ldc + col) * KOUT), out);
+                }
+            }
+}
+
+template <int KIN, int MODE>
+fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                            int64_t ldc, int M, int N, int K, hipStream_t stream)
+{
+    auto a = static_cast<const uint8_t*>(A);
+    auto b = static_cast<const uint8_t*>(B);
+    auto c = static_cast<uint8_t*>(C);
+    switch (kout) {
+        case 2: k_gemm_f64<KIN, 2, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 3: k_gemm_f64<KIN, 3, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 4: k_gemm_f64<KIN, 4, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 5: k_gemm_f64<KIN, 5, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 6: k_gemm_f64<KIN, 6, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 7: k_gemm_f64<KIN, 7, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        default: k_gemm_f64<KIN, 8, 0><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+    }
+    return check_launch("fb_gemm");
+}
+
+// Runs C = A B for operands packed in {64, KIN} with C in the format fc (valid,
+// binary64); sizes already checked against the tile.  Instantiated per KIN in
+// its own source file so the instantiations compile in parallel.
+template <int KIN>
+fb_status gemm_f64_run(fb_format fc, unsigned blocks, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                       int64_t ldc, int M, int N, int K, hipStream_t stream)
+{
+    return dispatch_round(fc, [&](auto rt) {
+        constexpr int MODE = decltype(rt)::value;
+        return launch_f64<KIN, MODE>(fc.k, blocks, A, lda, B, ldb, C, ldc, M, N, K, stream);
+    });
+}
+
+}  // namespace flyte

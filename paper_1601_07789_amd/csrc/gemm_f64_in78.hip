@@ -1,0 +1,11 @@
+// FP64 matrix-core GEMM instantiations for {64,7|8} operands.
+#include "gemm_f64_impl.hpp"
+
+namespace flyte {
+
+template fb_status gemm_f64_run<7>(fb_format, unsigned, const void*, int64_t, const void*, int64_t, void*, int64_t,
+                                      int, int, int, hipStream_t);
+template fb_status gemm_f64_run<8>(fb_format, unsigned, const void*, int64_t, const void*, int64_t, void*, int64_t,
+                                      int, int, int, hipStream_t);
+
+}  // namespace flyte

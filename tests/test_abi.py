@@ -97,7 +97,8 @@ def test_gemv_argument_errors(lib):
 def test_gemm_argument_errors(lib):
     args = (128, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128, None)
     assert lib.fb_gemm(F(32, 2), F(32, 3), F(32, 4), *args) == flyte.FB_ERR_UNSUPPORTED
-    assert lib.fb_gemm(F(64, 7), F(64, 7), F(64, 7), *args) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm(F(64, 7), F(32, 2), F(64, 7), *args) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm(F(64, 3), F(64, 3), F(32, 4), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(32, 2), F(32, 2), F(64, 8), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(64, 5), F(64, 6), F(64, 5), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(32, 2), F(32, 2), F(32, 4), 100, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128,

@@ -5,7 +5,7 @@ Error measures (componentwise-normwise, so near-zero entries do not blow up):
 Bounds (K inner dimension, u32 = 2^-24, u64 = 2^-53, gamma_n(u) = n u / (1 - n u)):
   BF16 ({32,2}):      products exact in FP32        -> e1 <= gamma_K(u32)
   3-product ({32,3}): |lo| < 2^-7 |x|, lo*lo dropped -> e1 <= 2^-14 + gamma_3K(u32) (1 + 2^-7)^2
-  FP64 ({64,5|6}):    |unpack(C) - C*| <= gamma_K(u64) (|A||B|) + 2^-(m+1) (|C*| + gamma_K(u64) (|A||B|))
+  FP64 ({64,2..8}):   |unpack(C) - C*| <= gamma_K(u64) (|A||B|) + 2^-(m+1) (|C*| + gamma_K(u64) (|A||B|))
 Integer-valued FP64 data is exact in FP64, so its packed C must equal the
 oracle's pack of the exact product bit for bit.
 """
@@ -80,10 +80,11 @@ def test_gemm_f64_integer_data_bit_exact(dev, orc):
     log("gemm f64 integer")
     M, N, K = 256, 256, 192
     g = np.random.default_rng(5)
-    Av = g.integers(-64, 65, (M, K)).astype(np.float64)
-    Bv = g.integers(-64, 65, (K, N)).astype(np.float64)
-    exact = Av @ Bv                        # exact: |C| < 2^20
-    for kin in (5, 6):
+    for kin in (2, 3, 4, 5, 6, 7, 8):
+        lim = 31 if kin == 2 else 64           # {64,2} holds integers up to 2^5 - 1 exactly
+        Av = g.integers(-lim, lim + 1, (M, K)).astype(np.float64)
+        Bv = g.integers(-lim, lim + 1, (K, N)).astype(np.float64)
+        exact = Av @ Bv                        # exact: |C| < 2^20
         A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
         Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
         for kout in (2, 3, 4, 5, 6, 7, 8):
@@ -92,13 +93,16 @@ def test_gemm_f64_integer_data_bit_exact(dev, orc):
             assert np.array_equal(C if kout < 8 else C.view(np.uint8), want), (kin, kout)
 
 
-@pytest.mark.parametrize("kin,kout", [(5, 5), (6, 6), (5, 8), (6, 3)])
+@pytest.mark.parametrize("kin,kout", [(5, 5), (6, 6), (5, 8), (6, 3), (2, 2), (3, 3), (4, 4), (2, 8), (4, 6), (7, 7),
+                                      (8, 8), (8, 5)])
 def test_gemm_f64_random_all_entries(dev, orc, kin, kout):
+    """Rows of A scaled over 2^-300 .. 2^300: the full binary64 exponent range of
+    the narrow formats, beyond what a bfloat16 split could carry."""
     import torch
     log(f"gemm f64 {kin}->{kout}")
     M, N, K = 128, 256, 208
     g = np.random.default_rng(7 + kin + kout)
-    Av = g.standard_normal((M, K)) * np.exp2(g.uniform(-30, 30, (M, 1)))
+    Av = g.standard_normal((M, K)) * np.exp2(np.round(g.uniform(-300, 300, (M, 1))))
     Bv = g.standard_normal((K, N))
     A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
     C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
