@@ -1,20 +1,39 @@
 // Transposed GEMV y = A^T x over a packed row-major A (m x n): y_j = sum_i
 // A_ij x_i, the other access order of the paper's BLAS level-2 kernel.
 //
-// A workgroup of 256 threads owns a strip of 256 consecutive column units and
-// a slab of consecutive rows; each thread walks its unit down the slab's rows
-// (U rows per loop trip), so every wave-wide load reads one contiguous span of
-// a row, and accumulates UNIT column sums with fma in the base type; x_i is
-// the same for the whole workgroup.  With more than one slab, the slab sums go
-// to a per-stream workspace and a second kernel adds them in slab order, so
-// the result is a fixed sequence of operations; the last step writes y native
-// or packed (one rounding, byte stores).
+// A workgroup of four waves owns a strip of 64 consecutive column units (one
+// unit per lane) and a slab of consecutive rows.  The slab's rows are dealt to
+// the waves in chunks of U rows (chunk c to wave c mod 4); a lane walks its
+// unit down its chunks, so every wave-wide load reads one contiguous span of
+// a row, and accumulates UNIT column sums with fma in the base type.  The
+// four wave sums are added in wave order through LDS.  With more than one
+// slab, the slab sums go to a per-stream workspace and a second kernel adds
+// them (slabs q = j mod 4 by thread group j, then the four groups in order),
+// so the result is a fixed sequence of operations for given sizes; the last
+// step writes y native or packed (one rounding, byte stores).  A is streamed
+// once, so units that one load instruction covers (at most 4 dwords) are read
+// non-temporally; 5- and 7-dword units are not, since their two instructions
+// share cache lines.
 #include "codec.hpp"
 #include "common.hpp"
+#include "gemv_impl.hpp"
 
 namespace flyte {
 
 constexpr int kGtBlock = 256;
+constexpr int kGtWaves = kGtBlock / 64;
+constexpr int kGtRows = 8;          // rows per chunk (loads in flight per lane)
+constexpr int kGtTarget = 1024;     // workgroups to aim for (strips x slabs)
+
+template <class F>
+__device__ __forceinline__ void gemv_t_store(typename F::native_t v, int64_t c, typename F::native_t* partial,
+                                             void* y, int yk, int ymode)
+{
+    using N = typename F::native_t;
+    if (partial) partial[c] = v;
+    else if (yk == 0) static_cast<N*>(y)[c] = v;
+    else store_bytes_rt(static_cast<uint8_t*>(y) + c * yk, pack_runtime((uint64_t)as_bits<F>(v), F::base, yk, ymode), yk);
+}
 
 template <class F, int U>
 __global__ void __launch_bounds__(kGtBlock)
@@ -23,22 +42,28 @@ k_gemv_t(const uint8_t* __restrict__ A, int64_t row_bytes, const void* __restric
 {
     using T = typename F::bits_t;
     using N = typename F::native_t;
+    __shared__ N red[kGtWaves - 1][F::UNIT][64];
     const N* x = static_cast<const N*>(xv);
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
     const int64_t nunits = n / F::UNIT;
-    const int64_t g = (int64_t)blockIdx.x * kGtBlock + threadIdx.x;     // column unit of this thread
+    const int64_t g = (int64_t)blockIdx.x * 64 + lane;     // column unit of this lane
     const int r0 = blockIdx.y * rows_per_slab;
     const int r1 = min(m, r0 + rows_per_slab);
+    const int tail = (int)(n - nunits * F::UNIT);          // columns after the last whole unit
     N acc[F::UNIT];
 #pragma unroll
     for (int e = 0; e < F::UNIT; ++e) acc[e] = N(0);
-    const int tail = (int)(n - nunits * F::UNIT);   // columns after the last whole unit
     if (g < nunits) {
-        int r = r0;
-        for (; r + U <= r1; r += U) {
+        const uint8_t* col = A + g * (F::UNIT_DW * 4);
+        int r = r0 + w * U;
+        for (; r + U <= r1; r += kGtWaves * U) {
             uint32_t P[U][F::UNIT_DW];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                load_dwords(reinterpret_cast<const uint32_t*>(A + (int64_t)(r + u) * row_bytes) + g * F::UNIT_DW, P[u]);
+                if constexpr (F::UNIT_DW <= 4)
+                    load_dwords_nt(reinterpret_cast<const uint32_t*>(col + (int64_t)(r + u) * row_bytes), P[u]);
+                else
+                    load_dwords(reinterpret_cast<const uint32_t*>(col + (int64_t)(r + u) * row_bytes), P[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 T ab[F::UNIT];
@@ -48,9 +73,9 @@ k_gemv_t(const uint8_t* __restrict__ A, int64_t row_bytes, const void* __restric
                 for (int e = 0; e < F::UNIT; ++e) acc[e] = fma_n(as_native<F>(ab[e]), xr, acc[e]);
             }
         }
-        for (; r < r1; ++r) {
+        for (; r < r1; ++r) {     // the slab's last, partial chunk (one wave at most)
             uint32_t P[F::UNIT_DW];
-            load_dwords(reinterpret_cast<const uint32_t*>(A + (int64_t)r * row_bytes) + g * F::UNIT_DW, P);
+            load_dwords(reinterpret_cast<const uint32_t*>(col + (int64_t)r * row_bytes), P);
             T ab[F::UNIT];
             unpack_elems<F, F::UNIT>(P, ab);
             const N xr = x[r];
@@ -58,27 +83,28 @@ k_gemv_t(const uint8_t* __restrict__ A, int64_t row_bytes, const void* __restric
             for (int e = 0; e < F::UNIT; ++e) acc[e] = fma_n(as_native<F>(ab[e]), xr, acc[e]);
         }
     } else if (g == nunits && tail > 0) {
-        for (int r = r0; r < r1; ++r) {
+        for (int r = r0 + w; r < r1; r += kGtWaves) {
             const uint8_t* row = A + (int64_t)r * row_bytes;
             const N xr = x[r];
             for (int e = 0; e < tail; ++e)
                 acc[e] = fma_n(as_native<F>(load_elem_unpacked<F>(row + (nunits * F::UNIT + e) * F::k)), xr, acc[e]);
         }
-    } else {
-        return;
     }
-    const int ncols = g < nunits ? F::UNIT : tail;
+    if (w > 0) {
+#pragma unroll
+        for (int e = 0; e < F::UNIT; ++e) red[w - 1][e][lane] = acc[e];
+    }
+    __syncthreads();
+    if (w > 0) return;
+    const int ncols = g < nunits ? F::UNIT : (g == nunits ? tail : 0);
+    N* dst = partial ? partial + (int64_t)blockIdx.y * n : nullptr;
 #pragma unroll
     for (int e = 0; e < F::UNIT; ++e) {
-        if (e >= ncols) break;
-        const int64_t c = g * F::UNIT + e;
-        if (partial) {
-            partial[(int64_t)blockIdx.y * n + c] = acc[e];
-        } else if (yk == 0) {
-            static_cast<N*>(y)[c] = acc[e];
-        } else {
-            store_bytes_rt(static_cast<uint8_t*>(y) + c * yk, pack_runtime((uint64_t)as_bits<F>(acc[e]), F::base, yk, ymode),
-                           yk);
+        if (e < ncols) {
+            N v = acc[e];
+#pragma unroll
+            for (int q = 0; q < kGtWaves - 1; ++q) v = v + red[q][e][lane];
+            gemv_t_store<F>(v, g * F::UNIT + e, dst, y, yk, ymode);
         }
     }
 }
@@ -89,12 +115,27 @@ k_gemv_t_final(const typename F::native_t* __restrict__ partial, int nslabs, int
                int ymode)
 {
     using N = typename F::native_t;
-    const int64_t c = (int64_t)blockIdx.x * kGtBlock + threadIdx.x;
-    if (c >= n) return;
+    __shared__ N red[kGtWaves - 1][64];
+    const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+    const int64_t c = (int64_t)blockIdx.x * 64 + lane;
     N s = N(0);
-    for (int q = 0; q < nslabs; ++q) s = s + partial[(int64_t)q * n + c];
-    if (yk == 0) static_cast<N*>(y)[c] = s;
-    else store_bytes_rt(static_cast<uint8_t*>(y) + c * yk, pack_runtime((uint64_t)as_bits<F>(s), F::base, yk, ymode), yk);
+    if (c < n) {
+        int q = w;
+        for (; q + 3 * kGtWaves < nslabs; q += 4 * kGtWaves) {     // four loads in flight, added in q order
+            N v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = partial[(int64_t)(q + i * kGtWaves) * n + c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) s = s + v[i];
+        }
+        for (; q < nslabs; q += kGtWaves) s = s + partial[(int64_t)q * n + c];
+    }
+    if (w > 0) red[w - 1][lane] = s;
+    __syncthreads();
+    if (w > 0 || c >= n) return;
+#pragma unroll
+    for (int q = 0; q < kGtWaves - 1; ++q) s = s + red[q][lane];
+    gemv_t_store<F>(s, c, nullptr, y, yk, ymode);
 }
 
 template <class F>
@@ -118,13 +159,15 @@ fb_status gemv_t_launch(fb_format fa, fb_format fy, int64_t m, int64_t n, const 
             k_zero_native<F><<<256, 256, 0, stream>>>(y, n, yk);
             return check_launch("fb_gemv_ex");
         }
-        const int64_t ncolunits = n / F::UNIT + 1;            // + the tail unit
-        const int64_t nstrips = (ncolunits + kGtBlock - 1) / kGtBlock;
-        int64_t nslabs = (2048 + nstrips - 1) / nstrips;       // aim for ~2048 workgroups
-        const int64_t max_slabs = (m + 15) / 16;               // at least 16 rows per slab
+        const int64_t ncolunits = n / F::UNIT + (n % F::UNIT ? 1 : 0);   // + the tail unit
+        const int64_t nstrips = (ncolunits + 63) / 64;
+        constexpr int64_t kChunkRows = (int64_t)kGtWaves * kGtRows;     // one chunk per wave
+        int64_t nslabs = (kGtTarget + nstrips - 1) / nstrips;
+        const int64_t max_slabs = (m + 2 * kChunkRows - 1) / (2 * kChunkRows);   // >= 2 chunks per wave
         if (nslabs > max_slabs) nslabs = max_slabs;
         if (nslabs < 1) nslabs = 1;
-        const int64_t rows = (m + nslabs - 1) / nslabs;
+        int64_t rows = (m + nslabs - 1) / nslabs;
+        rows = (rows + kChunkRows - 1) / kChunkRows * kChunkRows;        // slabs hold whole chunks
         nslabs = (m + rows - 1) / rows;
         N* partial = nullptr;
         if (nslabs > 1) {
@@ -134,11 +177,11 @@ fb_status gemv_t_launch(fb_format fa, fb_format fy, int64_t m, int64_t n, const 
             partial = static_cast<N*>(ws);
         }
         dim3 grid((unsigned)nstrips, (unsigned)nslabs);
-        k_gemv_t<F, 4><<<grid, kGtBlock, 0, stream>>>(static_cast<const uint8_t*>(A), lda * F::k, x, (int)m, (int)n,
+        k_gemv_t<F, kGtRows><<<grid, kGtBlock, 0, stream>>>(static_cast<const uint8_t*>(A), lda * F::k, x, (int)m, (int)n,
                                                        (int)rows, partial, y, yk, fy.round);
         if (partial)
-            k_gemv_t_final<F><<<(unsigned)((n + kGtBlock - 1) / kGtBlock), kGtBlock, 0, stream>>>(partial, (int)nslabs,
-                                                                                              (int)n, y, yk, fy.round);
+            k_gemv_t_final<F><<<(unsigned)((n + 63) / 64), kGtBlock, 0, stream>>>(partial, (int)nslabs, (int)n, y, yk,
+                                                                                fy.round);
         return check_launch("fb_gemv_ex");
     });
 }

@@ -64,7 +64,7 @@ def test_gemv_transposed(dev, orc, f):
     base, k = f
     log(f"gemv transposed {f}")
     G = 4 // np.gcd(4, k)
-    for m, n in [(1, 1), (3, 7), (17, 1029), (300, 255), (2000, 70), (64, 4099)]:
+    for m, n in [(1, 1), (3, 7), (17, 1029), (300, 255), (2000, 70), (64, 4099), (700, 2051), (3001, 9)]:
         lda = (n + G - 1) // G * G + G
         A = orc.pack(base, k, workloads.uniform(m * lda, m + n, dtype=native_dtype(base)))
         x = workloads.uniform(m, 3 * m + 1, dtype=native_dtype(base))
