@@ -3,30 +3,40 @@
 // C = A B, A M x K and B K x N row-major packed, C FP32 row-major.
 //  MODE 0 ({32,2}): the stored 2-byte patterns are bfloat16 operands as they
 //    are (the 16-bit flyte of Table 1 is bit-for-bit bfloat16).
-//  MODE 1 ({32,3}): the loader unpacks each 3-byte element to binary32 x and
-//    splits it into hi = x with its low 16 bits cleared (a bfloat16) and
-//    lo = x - hi (exact in binary32, and exactly a bfloat16 for biased
-//    exponent >= 9; rounded to nearest otherwise; 0 for Inf/NaN).  The tile
-//    product is hi*hi + hi*lo + lo*hi: three BF16 MFMAs per step into the same
-//    FP32 accumulators (lo*lo, below 2^-16 relative, is dropped).
+//  MODE 1 ({32,3}): each 3-byte element, unpacked to binary32 x, is split into
+//    hi = x with its low 16 bits cleared (a bfloat16) and lo = x - hi (exact
+//    in binary32, and exactly a bfloat16 for biased exponent >= 9; rounded to
+//    nearest otherwise; 0 for Inf/NaN).  The tile product is hi*hi + hi*lo +
+//    lo*hi: three BF16 MFMAs per step into the same FP32 accumulators (lo*lo,
+//    below 2^-16 relative, is dropped).
 //  MODE 2 ({32,3}, four products): MODE 1 plus lo*lo, so every product of the
 //    split operands is formed exactly and only the FP32 accumulation rounds.
+//
+// The split is done once per element by a streaming pass before the GEMM (A
+// into row-major hi/lo planes, B into n-major planes, transposed through LDS),
+// in the per-stream workspace; the GEMM loader then copies plane tiles to LDS
+// as they are.  Splitting inside the GEMM loader would repeat the split for
+// every tile of C that reads the element (N/BN times for A, M/BM for B), which
+// makes the split, not the matrix cores, the bound.
 //
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
 // wave tiles keep LDS operand traffic below the LDS bandwidth: BF16 uses
 // 256 x 256 x 64 tiles with 8 waves of 128 x 64 (about 94 B/clk of LDS reads
-// per CU at the MFMA peak, against 128 available); the 3-product uses
-// 256 x 128 x 32 with 4 waves of 128 x 64 (three MFMAs per operand pair);
-// shapes that are not multiples of those use 128 x 128 x 64.  K is walked in
-// BK steps through double-buffered LDS (one barrier per step; the next step's
-// global loads are issued before the current step's MFMAs; the last step is
-// peeled).  LDS rows are padded by 16 bytes, so the 16-byte operand reads of
-// 16 lanes hit distinct banks.  B is stored in LDS transposed (n-major, k contiguous):
-// each thread loads KR rows of B and transposes them in registers with
-// v_perm_b32, so every MFMA operand is one ds_read_b128.  Workgroups are
-// renumbered so that consecutive tiles of C run on the same XCD (sharing its
-// L2), grouped 8 tile-rows at a time.
+// per CU at the MFMA peak, against 128 available); the split products use
+// 256 x 128 x 32 with 4 waves of 128 x 64 (three or four MFMAs per operand
+// pair); shapes that are not multiples of those use 128 x 128 x 64.  K is
+// walked in BK steps through double-buffered LDS (one barrier per step; the
+// next step's global loads are issued before the current step's MFMAs; the
+// last step is peeled).  LDS rows are padded by 16 bytes, so the 16-byte
+// operand reads of 16 lanes hit distinct banks.  B is stored in LDS n-major
+// (k contiguous): for BF16 each thread loads KR rows of B and transposes them
+// in registers with v_perm_b32; the split planes of B are already n-major.
+// Every MFMA operand is one ds_read_b128.  Workgroups are renumbered so that
+// consecutive tiles of C run on the same XCD (sharing its L2), grouped 8
+// tile-rows at a time.
+#include <algorithm>
+
 #include "codec.hpp"
 #include "common.hpp"
 
@@ -85,23 +95,20 @@ struct B32Tile {
     static constexpr int TM = BM / WGM, TN = BN / WGN;
     static constexpr int FM = TM / 16, FN = TN / 16;
     static constexpr int PARTS = MODE ? 2 : 1;          // hi (and lo) operand tiles
-    static constexpr int KB = MODE ? 3 : 2;             // stored bytes per element
     static constexpr int ROW = BK + 8;                  // bf16 per padded LDS row
     static constexpr int A_TILE = BM * ROW, B_TILE = BN * ROW;
     static constexpr int STAGE = PARTS * (A_TILE + B_TILE);
-    // A: chunks of A_EL consecutive elements of a row (16 or 48 bytes)
-    static constexpr int A_EL = MODE ? 16 : 8;
-    static constexpr int A_CPR = BK / A_EL;
-    static constexpr int A_N = BM * A_CPR / THREADS;
-    static constexpr int A_DW = A_EL * KB / 4;
-    // B: groups of KR k-rows x BCOL columns (one dword or one 4-element unit per row)
-    static constexpr int BCOL = MODE ? 4 : 2;
-    static constexpr int B_GPR = BN / BCOL;
+    // A (and the B planes): chunks of 8 consecutive bf16 of a row (16 bytes)
+    static constexpr int CPR = BK / 8;
+    static constexpr int A_N = BM * CPR / THREADS;
+    static constexpr int BT_N = BN * CPR / THREADS;
+    // MODE 0 B: groups of KR k-rows x 2 columns (one dword per row)
+    static constexpr int B_GPR = BN / 2;
     static constexpr int B_G = (BK / KR) * B_GPR / THREADS;
-    static constexpr int B_DW = MODE ? 3 : 1;
     static_assert(BK % 32 == 0 && TM % 16 == 0 && TN % 16 == 0, "tile shape");
-    static_assert(A_N * THREADS == BM * A_CPR && A_N >= 1, "A staging must divide evenly");
-    static_assert(B_G * THREADS == (BK / KR) * B_GPR && B_G >= 1, "B staging must divide evenly");
+    static_assert(A_N * THREADS == BM * CPR && A_N >= 1, "A staging must divide evenly");
+    static_assert(MODE == 0 || (BT_N * THREADS == BN * CPR && BT_N >= 1), "B plane staging must divide evenly");
+    static_assert(MODE != 0 || (B_G * THREADS == (BK / KR) * B_GPR && B_G >= 1), "B staging must divide evenly");
     static_assert(KR == 4 || KR == 8, "B group rows");
 };
 
@@ -110,8 +117,11 @@ __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            float* __restrict__ C, int64_t ldc, int M, int N, int K)
 {
+    // MODE 0: A and B are the packed {32,2} matrices (bfloat16 patterns).
+    // MODE 1, 2: A = hi and lo planes [2][M][lda] of bfloat16; B = hi and lo
+    // planes [2][N][ldb] of B transposed (n-major).
     using T = B32Tile<MODE, BM, BN, BK, WGM, WGN, KR>;
-    constexpr int THREADS = T::THREADS, PARTS = T::PARTS, KB = T::KB, ROW = T::ROW;
+    constexpr int THREADS = T::THREADS, PARTS = T::PARTS, ROW = T::ROW;
     constexpr int FM = T::FM, FN = T::FN;
     // [stage][A hi, (A lo), B hi, (B lo)]
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][T::STAGE];
@@ -122,97 +132,80 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     const int m0 = tm * BM, n0 = tn * BN;
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
     const int wm = wid / WGN, wn = wid % WGN;
+    const int64_t a_plane = (int64_t)M * lda * 2, b_plane = (int64_t)N * ldb * 2;   // bytes
 
-    uint32_t ra[T::A_N][T::A_DW];
-    uint32_t rb[T::B_G][KR][T::B_DW];
+    uint32_t ra[PARTS][T::A_N][4];
+    constexpr int RB_N = MODE ? T::BT_N : 1;
+    uint32_t rbt[PARTS][RB_N][4];
+    constexpr int RB_G = MODE ? 1 : T::B_G;
+    uint32_t rb[RB_G][KR];
 
     auto a_tile = [&](int s, int part) { return lds[s] + part * T::A_TILE; };
     auto b_tile = [&](int s, int part) { return lds[s] + PARTS * T::A_TILE + part * T::B_TILE; };
 
     auto load_tiles = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < T::A_N; ++i) {
-            const int c = t + THREADS * i, row = c / T::A_CPR, kc = c % T::A_CPR;
-            load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * T::A_EL) * KB),
-                        ra[i]);
-        }
+        for (int p = 0; p < PARTS; ++p)
 #pragma unroll
-        for (int g = 0; g < T::B_G; ++g) {
-            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
+            for (int i = 0; i < T::A_N; ++i) {
+                const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
+                load_dwords(reinterpret_cast<const uint32_t*>(A + p * a_plane + ((int64_t)(m0 + row) * lda + k0 + kc * 8) * 2),
+                            ra[p][i]);
+            }
+        if constexpr (MODE == 0) {
 #pragma unroll
-            for (int r = 0; r < KR; ++r)
-                load_dwords(reinterpret_cast<const uint32_t*>(
-                                B + ((int64_t)(k0 + kg * KR + r) * ldb + n0 + T::BCOL * np) * KB),
-                            rb[g][r]);
+            for (int g = 0; g < T::B_G; ++g) {
+                const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
+#pragma unroll
+                for (int r = 0; r < KR; ++r)
+                    rb[g][r] = *reinterpret_cast<const uint32_t*>(B + ((int64_t)(k0 + kg * KR + r) * ldb + n0 + 2 * np) * 2);
+            }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p)
+#pragma unroll
+                for (int i = 0; i < T::BT_N; ++i) {
+                    const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
+                    load_dwords(reinterpret_cast<const uint32_t*>(B + p * b_plane +
+                                                                  ((int64_t)(n0 + row) * ldb + k0 + kc * 8) * 2),
+                                rbt[p][i]);
+                }
         }
     };
 
     auto store_tiles = [&](int s) {
-        uint16_t* Ah = a_tile(s, 0);
-        uint16_t* Bh = b_tile(s, 0);
 #pragma unroll
-        for (int i = 0; i < T::A_N; ++i) {
-            const int c = t + THREADS * i, row = c / T::A_CPR, kc = c % T::A_CPR;
-            if constexpr (MODE == 0) {
-                *reinterpret_cast<u32x4_t*>(Ah + row * ROW + kc * 8) = u32x4_t{ra[i][0], ra[i][1], ra[i][2], ra[i][3]};
-            } else {
-                using F = Fmt<32, 3>;
-                uint16_t* Al = a_tile(s, 1);
-                uint32_t x[16];
-                unpack_elems<F, 16>(ra[i], x);
-                uint32_t hi[8], lo[8];
+        for (int p = 0; p < PARTS; ++p)
 #pragma unroll
-                for (int e = 0; e < 16; e += 2) {
-                    uint32_t h0, l0, h1, l1;
-                    split_hi_lo(x[e], h0, l0);
-                    split_hi_lo(x[e + 1], h1, l1);
-                    hi[e / 2] = h0 | (h1 << 16);
-                    lo[e / 2] = l0 | (l1 << 16);
-                }
-                u32x4_t* dh = reinterpret_cast<u32x4_t*>(Ah + row * ROW + kc * 16);
-                u32x4_t* dl = reinterpret_cast<u32x4_t*>(Al + row * ROW + kc * 16);
-                dh[0] = u32x4_t{hi[0], hi[1], hi[2], hi[3]};
-                dh[1] = u32x4_t{hi[4], hi[5], hi[6], hi[7]};
-                dl[0] = u32x4_t{lo[0], lo[1], lo[2], lo[3]};
-                dl[1] = u32x4_t{lo[4], lo[5], lo[6], lo[7]};
+            for (int i = 0; i < T::A_N; ++i) {
+                const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
+                *reinterpret_cast<u32x4_t*>(a_tile(s, p) + row * ROW + kc * 8) =
+                    u32x4_t{ra[p][i][0], ra[p][i][1], ra[p][i][2], ra[p][i][3]};
             }
-        }
+        if constexpr (MODE == 0) {
+            uint16_t* Bh = b_tile(s, 0);
 #pragma unroll
-        for (int g = 0; g < T::B_G; ++g) {
-            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
-            if constexpr (MODE == 0) {
+            for (int g = 0; g < T::B_G; ++g) {
+                const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
                 // row r holds columns (2np, 2np+1) as low/high halves: transpose to k-contiguous columns
                 uint32_t c0[KR / 2], c1[KR / 2];
 #pragma unroll
                 for (int i = 0; i < KR / 2; ++i) {
-                    c0[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1][0], rb[g][2 * i][0], 0x05040100u);
-                    c1[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1][0], rb[g][2 * i][0], 0x07060302u);
+                    c0[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1], rb[g][2 * i], 0x05040100u);
+                    c1[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1], rb[g][2 * i], 0x07060302u);
                 }
                 store_row_chunk<KR>(Bh + (2 * np) * ROW + kg * KR, c0);
                 store_row_chunk<KR>(Bh + (2 * np + 1) * ROW + kg * KR, c1);
-            } else {
-                using F = Fmt<32, 3>;
-                uint16_t* Bl = b_tile(s, 1);
-                uint32_t hi[KR][4], lo[KR][4];   // [row][column]
-#pragma unroll
-                for (int r = 0; r < KR; ++r) {
-                    uint32_t x[4];
-                    unpack_elems<F, 4>(rb[g][r], x);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) split_hi_lo(x[c], hi[r][c], lo[r][c]);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    uint32_t vh[KR / 2], vl[KR / 2];
-#pragma unroll
-                    for (int i = 0; i < KR / 2; ++i) {
-                        vh[i] = hi[2 * i][c] | (hi[2 * i + 1][c] << 16);
-                        vl[i] = lo[2 * i][c] | (lo[2 * i + 1][c] << 16);
-                    }
-                    store_row_chunk<KR>(Bh + (4 * np + c) * ROW + kg * KR, vh);
-                    store_row_chunk<KR>(Bl + (4 * np + c) * ROW + kg * KR, vl);
-                }
             }
+        } else {
+#pragma unroll
+            for (int p = 0; p < PARTS; ++p)
+#pragma unroll
+                for (int i = 0; i < T::BT_N; ++i) {
+                    const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
+                    *reinterpret_cast<u32x4_t*>(b_tile(s, p) + row * ROW + kc * 8) =
+                        u32x4_t{rbt[p][i][0], rbt[p][i][1], rbt[p][i][2], rbt[p][i][3]};
+                }
         }
     };
 
@@ -273,6 +266,9 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     for (int kt = 0; kt < KT - 1; ++kt) {
         const int s = kt & 1;
         load_tiles((kt + 1) * BK);
+        // keep the next step's global loads ahead of this step's MFMAs, so
+        // their latency is covered by the whole step
+        __builtin_amdgcn_sched_barrier(0);
         compute(s);
         store_tiles(s ^ 1);
         __syncthreads();
@@ -290,6 +286,70 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                 const int col = n0 + wn * T::TN + j * 16 + lane % 16;
                 C[(int64_t)row * ldc + col] = acc[i][j][r];
             }
+}
+
+// Split pass for A ({32,3}, rows x cols, leading dimension ld elements): hi and
+// lo planes of bfloat16, row-major with leading dimension cols.  One lane per
+// 4-element unit (12 bytes in, 8 + 8 bytes out).
+__global__ void __launch_bounds__(256)
+k_split_rows(const uint8_t* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, uint16_t* __restrict__ hi,
+             uint16_t* __restrict__ lo)
+{
+    using F = Fmt<32, 3>;
+    const int64_t upr = cols / 4, total = rows * upr;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = q / upr, c4 = q % upr;
+        uint32_t P[3];
+        load_dwords(reinterpret_cast<const uint32_t*>(src + (row * ld + c4 * 4) * 3), P);
+        uint32_t x[4], h[4], l[4];
+        unpack_elems<F, 4>(P, x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) split_hi_lo(x[c], h[c], l[c]);
+        const int64_t o = row * cols + c4 * 4;
+        uint32_t hv[2] = {h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+        uint32_t lv[2] = {l[0] | (l[1] << 16), l[2] | (l[3] << 16)};
+        store_dwords(reinterpret_cast<uint32_t*>(hi + o), hv);
+        store_dwords(reinterpret_cast<uint32_t*>(lo + o), lv);
+    }
+}
+
+// Split pass for B ({32,3}, rows x cols, leading dimension ld elements) into
+// hi and lo planes of B transposed (cols x rows, leading dimension rows), 64 x
+// 64 tiles through LDS: a lane reads 4-element units of a row and writes the
+// split halves down LDS columns; then 16-byte chunks of the transposed rows go
+// out.  rows and cols are multiples of 64.
+__global__ void __launch_bounds__(256)
+k_split_cols_t(const uint8_t* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, uint16_t* __restrict__ hi,
+               uint16_t* __restrict__ lo)
+{
+    using F = Fmt<32, 3>;
+    constexpr int TP = 64 + 8;   // padded LDS row (bf16)
+    __shared__ __attribute__((aligned(16))) uint16_t tile[2][64][TP];   // [plane][col][row]
+    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int u = t + 256 * i, r = u / 16, cu = u % 16;
+        uint32_t P[3];
+        load_dwords(reinterpret_cast<const uint32_t*>(src + ((r0 + r) * ld + c0 + cu * 4) * 3), P);
+        uint32_t x[4];
+        unpack_elems<F, 4>(P, x);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t h, l;
+            split_hi_lo(x[c], h, l);
+            tile[0][cu * 4 + c][r] = (uint16_t)h;
+            tile[1][cu * 4 + c][r] = (uint16_t)l;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int idx = t + 256 * i, p = idx / 512, c = (idx % 512) / 8, ch = idx % 8;
+        const u32x4_t v = *reinterpret_cast<const u32x4_t*>(&tile[p][c][ch * 8]);
+        uint16_t* dst = (p ? lo : hi) + (c0 + c) * rows + r0 + ch * 8;
+        *reinterpret_cast<u32x4_t*>(dst) = v;
+    }
 }
 
 template <int MODE, int BM, int BN, int BK, int WGM, int WGN, int KR>
@@ -315,16 +375,30 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
             launch_b32<0, 256, 256, 64, 2, 4, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
         else
             launch_b32<0, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
-    } else if (mode == 1) {
-        if (M % 256 == 0)
-            launch_b32<1, 256, 128, 32, 2, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
-        else
-            launch_b32<1, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     } else {
-        if (M % 256 == 0)
-            launch_b32<2, 256, 128, 32, 2, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
-        else
-            launch_b32<2, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        // split both operands once into bfloat16 planes in the stream workspace
+        void* ws = nullptr;
+        const size_t bytes = (size_t)(M * K + N * K) * 4;
+        fb_status st = stream_workspace(stream, bytes, &ws);
+        if (st != FB_OK) return st;
+        uint16_t* ap = static_cast<uint16_t*>(ws);
+        uint16_t* bp = ap + 2 * M * K;
+        const int64_t units = M * (K / 4);
+        const unsigned sblocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
+        k_split_rows<<<sblocks, 256, 0, stream>>>(static_cast<const uint8_t*>(A), lda, M, K, ap, ap + M * K);
+        k_split_cols_t<<<dim3((unsigned)(N / 64), (unsigned)(K / 64)), 256, 0, stream>>>(
+            static_cast<const uint8_t*>(B), ldb, K, N, bp, bp + N * K);
+        if (mode == 1) {
+            if (M % 256 == 0)
+                launch_b32<1, 256, 128, 32, 2, 2, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
+            else
+                launch_b32<1, 128, 128, 64, 2, 2, 8>(M, N, K, ap, K, bp, K, C, ldc, stream);
+        } else {
+            if (M % 256 == 0)
+                launch_b32<2, 256, 128, 32, 2, 2, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
+            else
+                launch_b32<2, 128, 128, 64, 2, 2, 8>(M, N, K, ap, K, bp, K, C, ldc, stream);
+        }
     }
     return check_launch("fb_gemm");
 }
