@@ -56,7 +56,7 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
 }
 
 // ---------------------------------------------------------------- unpack
-template <class F, int U>
+template <class F, int U, int NE>
 __global__ void __launch_bounds__(kBlock)
 k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
 {
@@ -64,27 +64,27 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
-        uint32_t P[U][F::UNIT_DW];
+        uint32_t P[U][(NE * F::k / 4)];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_dwords(src + g * F::UNIT_DW, P[u]);
+            if (g < nunits) load_dwords(src + g * (NE * F::k / 4), P[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
             if (g < nunits) {
-                T b[F::UNIT];
-                unpack_elems<F, F::UNIT>(P[u], b);
-                uint32_t w[F::UNIT_NW];
-                bits_to_words<F, F::UNIT>(b, w);
-                store_dwords(dst + g * F::UNIT_NW, w);
+                T b[NE];
+                unpack_elems<F, NE>(P[u], b);
+                uint32_t w[(NE * F::W / 4)];
+                bits_to_words<F, NE>(b, w);
+                store_dwords(dst + g * (NE * F::W / 4), w);
             }
         });
     }
     if (blockIdx.x == 0) {
-        const int64_t i = nunits * F::UNIT + threadIdx.x;
-        if (threadIdx.x < F::UNIT && i < n) {
+        const int64_t i = nunits * NE + threadIdx.x;
+        if (threadIdx.x < NE && i < n) {
             const T u = load_elem_unpacked<F>(reinterpret_cast<const uint8_t*>(src) + i * F::k);
             if constexpr (F::W == 4) {
                 dst[i] = u;
@@ -291,7 +291,7 @@ static int stream_grid(int64_t nunits, int unroll)
 {
     const int64_t per_block = (int64_t)kBlock * unroll;
     int64_t blocks = (nunits + per_block - 1) / per_block;
-    const int64_t cap = (int64_t)device_cu_count() * 16;
+    const int64_t cap = (int64_t)device_cu_count() * 64;
     if (blocks > cap) blocks = cap;
     if (blocks < 1) blocks = 1;
     return (int)blocks;
@@ -338,8 +338,13 @@ extern "C" fb_status fb_unpack(fb_format f, const void* src_packed, void* dst_na
     if (st != FB_OK || n == 0) return st;
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
-        const int64_t nunits = (int64_t)(n / F::UNIT);
-        k_unpack<F, kUnroll><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+        // unpack writes W/k times what it reads, so its lane unit is sized by the
+        // output: 16 bytes (2 binary64 or 4 binary32 values) where whole dwords
+        // of input allow it, else 4 elements (odd k with binary64)
+        constexpr int NE = (F::base == 64) ? ((F::k % 2 == 0) ? 2 : 4) : 4;
+        static_assert(NE % F::G == 0, "unit must be whole dword groups");
+        const int64_t nunits = (int64_t)(n / NE);
+        k_unpack<F, kUnroll, NE><<<stream_grid(nunits, kUnroll), kBlock, 0, stream>>>(
             static_cast<const uint32_t*>(src_packed), static_cast<uint32_t*>(dst_native), nunits, (int64_t)n);
         return check_launch("fb_unpack");
     });
