@@ -21,11 +21,13 @@
 //
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
-// wave tiles keep LDS operand traffic below the LDS bandwidth: BF16 uses
-// 256 x 256 x 64 tiles with 8 waves of 128 x 64 (about 94 B/clk of LDS reads
-// per CU at the MFMA peak, against 128 available); the split products use
-// 256 x 128 x 32 with 4 waves of 128 x 64 (three or four MFMAs per operand
-// pair); shapes that are not multiples of those use 128 x 128 x 64.  K is
+// wave tiles keep LDS operand traffic below the LDS bandwidth (a 64 x 128 or
+// 128 x 64 wave tile reads about 94 B/clk of LDS per CU at the MFMA peak,
+// against 128 available).  256 x 256 x 32 tiles with 8 waves: BF16 as 4 x 2
+// waves of 64 x 128, the split products as 2 x 4 waves of 128 x 64 (their two
+// planes fill the 160 KiB of LDS exactly); the short K step keeps registers
+// for two waves per SIMD.  Shapes that are not multiples of 256 use 256 x 128
+// x 32 (split products, M a multiple of 256) or 128 x 128 x 64.  K is
 // walked in BK steps through double-buffered LDS (one barrier per step; the
 // next step's global loads are issued before the current step's MFMAs; the
 // last step is peeled).  LDS rows are padded by 16 bytes, so the 16-byte
@@ -372,7 +374,7 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
         return set_error(FB_ERR_ARG, "fb_gemm: sizes too large");
     if (mode == 0) {
         if (M % 256 == 0 && N % 256 == 0)
-            launch_b32<0, 256, 256, 64, 2, 4, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+            launch_b32<0, 256, 256, 32, 4, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
         else
             launch_b32<0, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     } else {
@@ -389,12 +391,16 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
         k_split_cols_t<<<dim3((unsigned)(N / 64), (unsigned)(K / 64)), 256, 0, stream>>>(
             static_cast<const uint8_t*>(B), ldb, K, N, bp, bp + N * K);
         if (mode == 1) {
-            if (M % 256 == 0)
+            if (M % 256 == 0 && N % 256 == 0)
+                launch_b32<1, 256, 256, 32, 2, 4, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
+            else if (M % 256 == 0)
                 launch_b32<1, 256, 128, 32, 2, 2, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
             else
                 launch_b32<1, 128, 128, 64, 2, 2, 8>(M, N, K, ap, K, bp, K, C, ldc, stream);
         } else {
-            if (M % 256 == 0)
+            if (M % 256 == 0 && N % 256 == 0)
+                launch_b32<2, 256, 256, 32, 2, 4, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
+            else if (M % 256 == 0)
                 launch_b32<2, 256, 128, 32, 2, 2, 4>(M, N, K, ap, K, bp, K, C, ldc, stream);
             else
                 launch_b32<2, 128, 128, 64, 2, 2, 8>(M, N, K, ap, K, bp, K, C, ldc, stream);
