@@ -45,7 +45,8 @@
  *  - Nothing aborts, throws or prints.  Hot calls allocate no device memory,
  *    except a per-(device, stream) workspace for partial sums (fb_dot,
  *    fb_dot_packed, fb_nrm2: 16 KiB; transposed fb_gemv_ex: slabs * n native
- *    values), allocated on first use on that stream and kept; growing it
+ *    values; {32,3} fb_gemm: the split operands, (M*K + K*N) * 4 bytes),
+ *    allocated on first use on that stream and kept; growing it
  *    synchronises the stream.
  *  - Input and output ranges must not overlap unless a call says so.
  */
@@ -242,18 +243,25 @@ void fb_plan_destroy(fb_plan *plan);
 
 /* ------------------------------------------------------------------ BLAS 3 */
 
-/* C = A B with A M x K (lda), B K x N (ldb), C M x N (ldc), row-major.
+/* C = A B with A M x K (lda), B K x N (ldb), C M x N (ldc), row-major: the
+ * matrix-matrix benchmark of Section 6 with the codec fused into the operand
+ * loaders and, for a packed C, into the epilogue (Sections 3.2, 5.2).
  * Supported combinations (others: FB_ERR_UNSUPPORTED):
  *  - fa = fb = {32,2}, fc = {32,4}: the stored 2-byte patterns are bfloat16
  *    operands of BF16 matrix-core instructions, FP32 accumulation, FP32 C.
- *  - fa = fb = {32,3}, fc = {32,4}: each operand is split while loading into
- *    hi = its top two bytes (a bfloat16) and lo = x - hi (exact, and exactly a
- *    bfloat16 for normal x with biased exponent >= 9); C = hi*hi + hi*lo +
- *    lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
- *  - fa = fb = {64,5} or {64,6}, fc any binary64 format: operands unpacked to
- *    FP64, FP64 matrix-core products and accumulation, C rounded to fc in the
- *    epilogue in fc's rounding mode (one rounding of the FP64 result).
- * M, N, K >= 0; M and N must be multiples of 4 for a packed C with k < 8. */
+ *  - fa = fb = {32,3}, fc = {32,4}: each operand element is split into hi =
+ *    its top two bytes (a bfloat16) and lo = x - hi rounded to bfloat16 (exact
+ *    for normal x with biased exponent >= 9; 0 for Inf/NaN); C = hi*hi +
+ *    hi*lo + lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
+ *    The split is written once to the stream workspace ((M*K + K*N) * 4
+ *    bytes) by a pass before the products.
+ *  - fa = fb = any binary64 format {64,2..8}, fc any binary64 format: operands
+ *    unpacked to FP64, FP64 matrix-core products and accumulation (products
+ *    exact for k <= 4), C rounded to fc in the epilogue in fc's rounding mode
+ *    (one rounding of the FP64 result).
+ * Sizes: M, N multiples of 128; K a multiple of 64 (binary32) or 16
+ * (binary64); other shapes FB_ERR_UNSUPPORTED.  K = 0 gives C = +0.  Rows of
+ * A, B and C start 4-byte aligned (ld * k a multiple of 4), else FB_ERR_ALIGN. */
 fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
                   const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
                   hipStream_t stream);
