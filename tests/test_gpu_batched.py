@@ -137,3 +137,48 @@ def test_empty_and_zero_row_batches(dev):
     plan.launch()
     torch.cuda.synchronize()
     plan.close()
+
+
+def test_batched_benchmark_size_sampled(dev, orc):
+    """The 4096-GEMV workload the benchmark times (same generator, seeds and input
+    construction), tuned and launched as the persistent graph: every y equals the
+    per-call fb_gemv_config of its plan tile bit for bit, and 6 rows of each of 24
+    sampled descriptors meet the summation bound against the exact oracle."""
+    import torch
+    log("batched 4096 benchmark workload")
+    descs = workloads.batched_descs(4096, workloads.SEED_BASE + 3)
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 3)
+    pool = {32: torch.empty(4096 * 4096, dtype=torch.float32, device=dev).uniform_(-1, 1, generator=g),
+            64: torch.empty(4096 * 4096, dtype=torch.float64, device=dev).uniform_(-1, 1, generator=g)}
+    items = []
+    for d in descs:
+        f = (d["base"], d["k"])
+        src = pool[d["base"]][: d["m"] * d["lda"]]
+        A = flyte.pack(f, src)
+        x = pool[d["base"]][1000: 1000 + d["n"]].clone()
+        y = torch.full((d["m"],), float("nan"), dtype=src.dtype, device=dev)
+        items.append(flyte.GemvItem(f, d["m"], d["n"], d["lda"], A, x, y))
+    del pool
+    plan = flyte.BatchedGemv(items)
+    plan.tune(reps=3)
+    plan.launch()
+    torch.cuda.synchronize()
+    ref = per_call(items, plan)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        assert same_bits(it.y, ref[i]), (i, it.f, it.m, it.n, plan.config(i))
+    rng = np.random.default_rng(11)
+    for i in rng.choice(len(items), 24, replace=False):
+        it = items[i]
+        base, k = it.f
+        rows = np.unique(np.concatenate([[0, it.m - 1], rng.integers(0, it.m, 4)]))
+        rb = torch.from_numpy((rows[:, None] * (it.lda * k) + np.arange(it.lda * k)[None, :]).reshape(-1)).to(dev)
+        sub = it.A[rb].cpu().numpy()
+        exact, absrow = orc.gemv_exact(base, k, len(rows), it.n, sub, it.lda, it.x.cpu().numpy())
+        got = it.y.cpu().numpy()[rows].astype(np.float64)
+        bound = gamma(max(it.n, 1), base) * absrow + unit_roundoff(base) * np.abs(exact)
+        assert np.all(np.abs(got - exact) <= bound), (i, it.f, it.m, it.n)
+    plan.close()
+    del items, ref
+    torch.cuda.empty_cache()

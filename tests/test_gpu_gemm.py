@@ -164,7 +164,7 @@ def test_gemm_binary32_benchmark_size_sampled(dev, orc, k):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("k", [5, 6])
+@pytest.mark.parametrize("k", [5, 6, 3])
 def test_gemm_f64_benchmark_size_sampled(dev, orc, k):
     """M = N = K = 16384, N(0,1) entries, C packed to the same k: sampled entries."""
     import torch

@@ -4,6 +4,9 @@ streaming workload (sampled rows) in the launch configuration the benchmark
 uses."""
 from __future__ import annotations
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -82,12 +85,28 @@ def test_gemv_empty(dev):
     assert torch.all(y == 0).item()
 
 
+TILE_CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1601_07789_amd",
+                          "tuned", "gemv_mi355x.json")
+
+
+@pytest.fixture()
+def bench_tiles():
+    """The committed tile cache that the benchmark loads, for the length of a test."""
+    flyte.tune_load(TILE_CACHE)
+    with open(TILE_CACHE) as fh:
+        entries = json.load(fh)["entries"]
+    yield {(e["base"], e["k"]): e["tile"] for e in entries}
+    flyte.tune_clear()
+
+
 @pytest.mark.parametrize("k", [3, 4, 5, 6, 7, 8])
-def test_gemv_streaming_size_sampled(dev, orc, k):
-    """A 8192 x 8192 (binary64-derived k bytes, U(-1,1)), x U(-1,1): 48 sampled rows."""
+def test_gemv_streaming_size_sampled(dev, orc, bench_tiles, k):
+    """A 8192 x 8192 (binary64-derived k bytes, U(-1,1)), x U(-1,1): 48 sampled rows,
+    with the tile the benchmark runs (the committed cache)."""
     import torch
     log(f"gemv 8192^2 k={k}")
     m = n = 8192
+    assert flyte.tune_lookup((64, k), m, n) == bench_tiles[(64, k)]
     g = torch.Generator(device=dev)
     g.manual_seed(workloads.SEED_BASE + 1)
     vals = torch.empty(m * n, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=g)
