@@ -317,9 +317,10 @@ k_split_rows(const uint8_t* __restrict__ src, int64_t ld, int64_t rows, int64_t 
 
 // Split pass for B ({32,3}, rows x cols, leading dimension ld elements) into
 // hi and lo planes of B transposed (cols x rows, leading dimension rows), 64 x
-// 64 tiles through LDS: a lane reads 4-element units of a row and writes the
-// split halves down LDS columns; then 16-byte chunks of the transposed rows go
-// out.  rows and cols are multiples of 64.
+// 64 tiles through LDS (blockIdx.x: tile row, blockIdx.y: tile column): a lane
+// reads 4-element units of a row and writes the split halves down LDS columns;
+// then 16-byte chunks of the transposed rows go out.  rows and cols are
+// multiples of 64.
 __global__ void __launch_bounds__(256)
 k_split_cols_t(const uint8_t* __restrict__ src, int64_t ld, int64_t rows, int64_t cols, uint16_t* __restrict__ hi,
                uint16_t* __restrict__ lo)
@@ -327,7 +328,7 @@ k_split_cols_t(const uint8_t* __restrict__ src, int64_t ld, int64_t rows, int64_
     using F = Fmt<32, 3>;
     constexpr int TP = 64 + 8;   // padded LDS row (bf16)
     __shared__ __attribute__((aligned(16))) uint16_t tile[2][64][TP];   // [plane][col][row]
-    const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+    const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
     const int t = threadIdx.x;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -372,6 +373,8 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
     if (M == 0 || N == 0) return FB_OK;
     if ((M / 128) * (N / 128) > INT32_MAX || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
         return set_error(FB_ERR_ARG, "fb_gemm: sizes too large");
+    if (mode != 0 && N / 64 > 65535)   // grid.y of the split pass of B
+        return set_error(FB_ERR_UNSUPPORTED, "fb_gemm: {32,3} operands need N <= %d", 65535 * 64);
     if (mode == 0) {
         if (M % 256 == 0 && N % 256 == 0)
             launch_b32<0, 256, 256, 32, 4, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
@@ -388,7 +391,7 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
         const int64_t units = M * (K / 4);
         const unsigned sblocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
         k_split_rows<<<sblocks, 256, 0, stream>>>(static_cast<const uint8_t*>(A), lda, M, K, ap, ap + M * K);
-        k_split_cols_t<<<dim3((unsigned)(N / 64), (unsigned)(K / 64)), 256, 0, stream>>>(
+        k_split_cols_t<<<dim3((unsigned)(K / 64), (unsigned)(N / 64)), 256, 0, stream>>>(
             static_cast<const uint8_t*>(B), ldb, K, N, bp, bp + N * K);
         if (mode == 1) {
             if (M % 256 == 0 && N % 256 == 0)
