@@ -438,7 +438,8 @@ def bench_batched(flyte, workloads, torch, dev, stream):
 
 
 def bench_gemm(flyte, workloads, torch, np, dev, stream):
-    """TFLOP/s of the three GEMM paths (2*M*N*K useful flop per call)."""
+    """TFLOP/s of the GEMM paths (2*M*N*K useful flop per call), with the vendor
+    library's bfloat16 and FP64 GEMMs at the same sizes beside them."""
     out = {}
 
     def timed(fn, reps):
@@ -465,6 +466,13 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
         out[name] = {"M": Mg, "N": Mg, "K": Mg, "ms": round(ms, 3),
                      "TFLOPs": round(2.0 * Mg ** 3 / (ms * 1e-3) / 1e12, 1)}
         del Ap, Bp, C
+    # the vendor library's bfloat16 GEMM at the same size (context, not a path of this library)
+    a16 = torch.empty(Mg, Mg, dtype=torch.float32, device=dev).normal_(generator=g).bfloat16()
+    b16 = torch.empty(Mg, Mg, dtype=torch.float32, device=dev).normal_(generator=g).bfloat16()
+    ms = timed(lambda: torch.matmul(a16, b16), 10)
+    out["vendor_bf16_matmul"] = {"M": Mg, "N": Mg, "K": Mg, "ms": round(ms, 3),
+                                 "TFLOPs": round(2.0 * Mg ** 3 / (ms * 1e-3) / 1e12, 1)}
+    del a16, b16
     g.manual_seed(workloads.SEED_BASE + 4)
     Mf = 16384
     for k in (5, 6, 3):
@@ -478,6 +486,13 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
         out[f"fp64_k{k}"] = {"M": Mf, "N": Mf, "K": Mf, "ms": round(ms, 2),
                              "TFLOPs": round(2.0 * Mf ** 3 / (ms * 1e-3) / 1e12, 2)}
         del Ap, Bp, C
+    # the vendor library's FP64 GEMM at the same size (native FP64 operands and C)
+    a64 = torch.empty(Mf, Mf, dtype=torch.float64, device=dev).normal_(generator=g)
+    b64 = torch.empty(Mf, Mf, dtype=torch.float64, device=dev).normal_(generator=g)
+    ms = timed(lambda: torch.matmul(a64, b64), 2)
+    out["vendor_fp64_matmul"] = {"M": Mf, "N": Mf, "K": Mf, "ms": round(ms, 2),
+                                 "TFLOPs": round(2.0 * Mf ** 3 / (ms * 1e-3) / 1e12, 2)}
+    del a64, b64
     torch.cuda.empty_cache()
     return out
 
