@@ -254,7 +254,9 @@ void fb_plan_destroy(fb_plan *plan);
  *    for normal x with biased exponent >= 9; 0 for Inf/NaN); C = hi*hi +
  *    hi*lo + lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
  *    The split is written once to the stream workspace ((M*K + K*N) * 4
- *    bytes) by a pass before the products.
+ *    bytes) by a pass before the products.  An infinite element (hi = Inf,
+ *    lo = 0) can meet a partner whose lo is 0 in a hi*lo term, Inf * 0, so
+ *    entries whose exact value is +-Inf may come out NaN; NaN stays NaN.
  *  - fa = fb = any binary64 format {64,2..8}, fc any binary64 format: operands
  *    unpacked to FP64, FP64 matrix-core products and accumulation (products
  *    exact for k <= 4), C rounded to fc in the epilogue in fc's rounding mode

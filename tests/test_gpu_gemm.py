@@ -188,3 +188,89 @@ def test_gemm_f64_benchmark_size_sampled(dev, orc, k):
     assert np.all(np.abs(got - ce) <= bound * (1 + 1e-12))
     del A, B, C
     torch.cuda.empty_cache()
+
+
+def _special_entries(orc, fa, K, A, B, N, M):
+    ii, jj = all_entries(M, N)
+    return orc.gemm_entries(fa, fa, K, A, K, B, N, ii, jj)
+
+
+def test_gemm_bf16_subnormal_operands(dev, orc):
+    """{32,2} rows of A made of bfloat16 subnormals (m * 2^-133) against B ~ 2^60..2^90, so
+    every product is a normal binary32 number: the products stay exact only if the matrix
+    cores keep subnormal inputs (a flush would zero those rows, e1 ~ 1)."""
+    import torch
+    M, N, K = 128, 128, 64
+    g = np.random.default_rng(21)
+    Av = (g.standard_normal((M, K)) * np.exp2(np.round(g.uniform(-20, 10, (M, 1))))).astype(np.float32)
+    sub = (g.integers(1, 128, (M // 2, K)) * g.choice([-1.0, 1.0], (M // 2, K))).astype(np.float64) * 2.0 ** -133
+    Av[M // 2:] = sub.astype(np.float32)
+    Bv = (g.standard_normal((K, N)) * np.exp2(np.round(g.uniform(60, 90, (1, N))))).astype(np.float32)
+    A, B = orc.pack(32, 2, Av.reshape(-1)), orc.pack(32, 2, Bv.reshape(-1))
+    assert np.array_equal(orc.unpack(32, 2, A).reshape(M, K)[M // 2:], Av[M // 2:])   # exactly bfloat16
+    C = flyte.gemm((32, 2), (32, 2), (32, 4), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
+    C = C.cpu().numpy().astype(np.float64)
+    ce, cab = _special_entries(orc, (32, 2), K, A, B, N, M)
+    e1 = np.abs(C - ce) / cab
+    assert np.max(e1[: M * N // 2]) <= gam(K, U32)
+    assert np.max(e1[M * N // 2:]) <= gam(K, U32), "subnormal bfloat16 inputs were not kept"
+
+
+def test_gemm_f64_subnormal_operands(dev, orc):
+    """{64,5} rows of A made of binary64 subnormals (~2^-1060) against B ~ 2^100: products
+    are normal, so FP64 matrix cores that keep subnormal inputs stay within the bound."""
+    import torch
+    M, N, K = 128, 128, 64
+    g = np.random.default_rng(22)
+    Av = g.standard_normal((M, K))
+    Av[M // 2:] *= 2.0 ** -1060
+    Bv = g.standard_normal((K, N)) * 2.0 ** 100
+    A, B = orc.pack(64, 5, Av.reshape(-1)), orc.pack(64, 5, Bv.reshape(-1))
+    C = flyte.gemm((64, 5), (64, 5), (64, 8), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
+    ce, cab = _special_entries(orc, (64, 5), K, A, B, N, M)
+    err = np.abs(C.cpu().numpy().reshape(-1) - ce)
+    assert np.all(err <= gam(K, U64) * cab * (1 + 1e-12) + 2.0 ** -1074)
+
+
+@pytest.mark.parametrize("case", ["bf16", "three", "four", "f64"])
+def test_gemm_special_values(dev, orc, case):
+    """Inf, -Inf and NaN operands (and zeros beside them): entries whose exact value is NaN
+    are NaN, finite ones meet the bound.  Exact infinities are reproduced by the BF16 and
+    FP64 paths; the split products give NaN or the infinity, since the hi*lo term of an
+    infinite element's partner can be Inf * 0."""
+    import torch
+    M, N, K = 128, 128, 64
+    g = np.random.default_rng(23)
+    base, k = (64, 5) if case == "f64" else (32, 2 if case == "bf16" else 3)
+    dt = np.float64 if base == 64 else np.float32
+    Av = g.standard_normal((M, K)).astype(dt)
+    Bv = g.standard_normal((K, N)).astype(dt)
+    Av[3, 5], Av[70, 9], Av[100, 40] = np.inf, -np.inf, np.nan
+    Bv[5, 7] = 0.0             # Inf * 0 in entry (3, 7)
+    Bv[11, 100] = np.inf       # row 11 of B meets every row of A
+    Bv[12, 100] = -np.inf      # Inf - Inf in column 100
+    Bv[20, 50] = np.nan
+    A, B = orc.pack(base, k, Av.reshape(-1)), orc.pack(base, k, Bv.reshape(-1))
+    fc = (64, 8) if base == 64 else (32, 4)
+    flags = flyte.GEMM_FOUR_PRODUCTS if case == "four" else 0
+    C = flyte.gemm((base, k), (base, k), fc, M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+                   flags=flags).cpu().numpy().astype(np.float64).reshape(-1)
+    ce, cab = _special_entries(orc, (base, k), K, A, B, N, M)
+    nan, inf = np.isnan(ce), np.isinf(ce)
+    assert nan.sum() > 0 and inf.sum() > 0
+    assert np.all(np.isnan(C[nan]))
+    if case in ("bf16", "f64"):
+        assert np.array_equal(C[inf], ce[inf])
+    else:
+        assert np.all(np.isnan(C[inf]) | (C[inf] == ce[inf]))
+    fin = ~(nan | inf)
+    if case == "bf16":
+        bound = gam(K, U32)
+    elif case == "three":
+        bound = 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2
+    elif case == "four":
+        bound = gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2
+    else:
+        bound = gam(K, U64)
+    assert np.all(np.isfinite(C[fin]))
+    assert np.max(np.abs(C[fin] - ce[fin]) / cab[fin]) <= bound
