@@ -325,7 +325,26 @@ def cpu_baseline(A, x, np):
     gbs = total_bytes / total_s / 1e9
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle fbo_gemv_naive (one thread), full 8192x8192 GEMV per k = 3..8, "
-                      f"passes per k = {passes}; {total_s:.1f} s of CPU time"}
+                      f"passes per k = {passes}; {total_s:.1f} s of CPU time",
+            "host": host_cpu()}
+
+
+def host_cpu():
+    """CPU model and logical CPU count of the host the baseline ran on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        avail = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "available": avail}
 
 
 def bench_blas1(flyte, workloads, torch, dev, stream):
