@@ -35,9 +35,11 @@ const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks);
 int tune_bucket(int64_t v);
 
 // Tiles compiled into the persistent kernel (public GEMV config ids); the
-// order is the slot order of run_format below.  The set is kept light in
-// registers (the kernel's register budget is the largest of its paths) so
-// three workgroups fit per CU without spilling.
+// order is the slot order of run_format below.  The set keeps the kernel at
+// three workgroups per CU without spilling (the kernel's register budget is
+// the largest of its paths).  A set of two-row tiles only fits four
+// workgroups per CU but measured slower: the four-row tiles' reuse of x is
+// worth more than the extra occupancy.
 constexpr int kBatchedNumTiles = 8;
 static const int kBatchedTile[kBatchedNumTiles] = {11, 12, 9, 10, 33, 32, 21, 7};
 

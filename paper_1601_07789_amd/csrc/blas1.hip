@@ -3,10 +3,13 @@
 // rounding mode of the format as a template parameter.
 //
 // Every kernel walks the array in units of F::UNIT elements (whole dwords of
-// packed data).  Thread t of a grid of T threads handles units t, t + T, ...,
-// U of them per loop trip, so each wave-wide memory instruction touches one
-// contiguous span.  The fewer than UNIT elements after the last whole unit are
-// handled one by one with byte accesses by the first threads of block 0.
+// packed data); unpack, which writes W/k times what it reads, uses a unit
+// sized by its 16-byte output instead.  Thread t of a grid of T threads
+// handles units t, t + T, ..., U of them per loop trip, so each wave-wide
+// memory instruction touches one contiguous span; the grid is capped at 64
+// workgroups per CU.  The fewer than a unit of elements after the last whole
+// unit are handled one by one with byte accesses by the first threads of
+// block 0.
 #include "codec.hpp"
 #include "common.hpp"
 
