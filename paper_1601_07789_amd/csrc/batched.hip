@@ -96,13 +96,17 @@ __global__ void __launch_bounds__(kGemvBlock, 3)
 k_gemv_batched(const DescDev* __restrict__ descs, const WorkItem* __restrict__ items, int32_t nitems,
                uint32_t* __restrict__ counter)
 {
+    // The next item is claimed before the current one is processed, so the
+    // atomic's round trip overlaps the work; a workgroup claims one item past
+    // the end before it leaves (the counter is reset before every launch).
     __shared__ int32_t s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int32_t it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (it >= nitems) break;
+    if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(counter, 1u);
+    __syncthreads();
+    int32_t it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    while (it < nitems) {
+        uint32_t next = 0;
+        if (threadIdx.x == 0) next = atomicAdd(counter, 1u);
         const WorkItem w = items[it];
         const DescDev d = descs[w.desc];
         const int code = __builtin_amdgcn_readfirstlane(d.code);
@@ -119,6 +123,10 @@ k_gemv_batched(const DescDev* __restrict__ descs, const WorkItem* __restrict__ i
             case 8: run_format<64, 7>(d, slot, w.row0); break;
             default: run_format<64, 8>(d, slot, w.row0); break;
         }
+        if (threadIdx.x == 0) s_item = (int32_t)next;
+        __syncthreads();
+        it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
     }
 }
 
