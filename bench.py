@@ -461,8 +461,10 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
     library's bfloat16 and FP64 GEMMs at the same sizes beside them."""
     out = {}
 
-    def timed(fn, reps):
-        fn()
+    def timed(fn, reps, warm=1):
+        # untimed calls first: the GPU clock takes a few milliseconds of load to settle
+        for _ in range(warm):
+            fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -481,14 +483,14 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream):
         Ap, Bp = flyte.pack((32, k), Av), flyte.pack((32, k), Bv)
         del Av, Bv
         C = torch.empty(Mg * Mg, dtype=torch.float32, device=dev)
-        ms = timed(lambda: flyte.gemm((32, k), (32, k), (32, 4), Mg, Mg, Mg, Ap, Bp, C, flags=flags), 10)
+        ms = timed(lambda: flyte.gemm((32, k), (32, k), (32, 4), Mg, Mg, Mg, Ap, Bp, C, flags=flags), 10, warm=10)
         out[name] = {"M": Mg, "N": Mg, "K": Mg, "ms": round(ms, 3),
                      "TFLOPs": round(2.0 * Mg ** 3 / (ms * 1e-3) / 1e12, 1)}
         del Ap, Bp, C
     # the vendor library's bfloat16 GEMM at the same size (context, not a path of this library)
     a16 = torch.empty(Mg, Mg, dtype=torch.float32, device=dev).normal_(generator=g).bfloat16()
     b16 = torch.empty(Mg, Mg, dtype=torch.float32, device=dev).normal_(generator=g).bfloat16()
-    ms = timed(lambda: torch.matmul(a16, b16), 10)
+    ms = timed(lambda: torch.matmul(a16, b16), 10, warm=10)
     out["vendor_bf16_matmul"] = {"M": Mg, "N": Mg, "K": Mg, "ms": round(ms, 3),
                                  "TFLOPs": round(2.0 * Mg ** 3 / (ms * 1e-3) / 1e12, 1)}
     del a16, b16
