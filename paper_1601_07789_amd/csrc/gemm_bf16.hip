@@ -123,6 +123,11 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     // MODE 1, 2: A = hi and lo planes [2][M][lda] of bfloat16; B = hi and lo
     // planes [2][N][ldb] of B transposed (n-major).
     using T = B32Tile<MODE, BM, BN, BK, WGM, WGN, KR>;
+    // The split products hold hi and lo fragments of both operands; an (empty)
+    // statement that clobbers an accumulation register makes the compiler keep
+    // the MFMA accumulators in AGPRs, which leaves the fragments room in the
+    // VGPRs (no spills at two waves per SIMD).
+    if constexpr (MODE != 0) asm volatile("; accumulators in AGPRs" ::: "a0");
     constexpr int THREADS = T::THREADS, PARTS = T::PARTS, ROW = T::ROW;
     constexpr int FM = T::FM, FN = T::FN;
     // [stage][A hi, (A lo), B hi, (B lo)]
