@@ -238,7 +238,8 @@ int64_t fb_plan_bytes(const fb_plan *plan);
 /* Tile configuration chosen for descriptor i (or -1). */
 int32_t fb_plan_config(const fb_plan *plan, int32_t i);
 
-/* Frees the plan's device memory and graphs (synchronises its streams). */
+/* Frees the plan's device memory and graphs; waits for all work on the plan's device
+ * first (hipDeviceSynchronize), so a launch still in flight is not cut short. */
 void fb_plan_destroy(fb_plan *plan);
 
 /* ------------------------------------------------------------------ BLAS 3 */
