@@ -35,8 +35,9 @@
  *  - "native" means float for base 32 and double for base 64.
  *  - All data pointers are DEVICE pointers owned by the caller.  Every
  *    pointer must be 4-byte aligned, and every packed matrix row must start on
- *    a 4-byte boundary ((ld*k) % 4 == 0); otherwise FB_ERR_ALIGN.  Kernels use
- *    wider accesses when pointers and rows are 16-byte aligned.
+ *    a 4-byte boundary ((ld*k) % 4 == 0); otherwise FB_ERR_ALIGN.  Kernels
+ *    read and write whole dwords (up to 4 per instruction) at 4-byte aligned
+ *    addresses, so no stronger alignment is needed.
  *  - All calls are asynchronous on `stream` (0 = the null stream).  Argument
  *    errors are detected on the host, return immediately and launch nothing.
  *    A launch failure returns FB_ERR_RUNTIME.  Details of the last error on
@@ -102,7 +103,8 @@ fb_status fb_unpack(fb_format f, const void *src_packed, void *dst_native, size_
 
 /* ------------------------------------------------------------------ BLAS 1 */
 
-/* result = sum_i unpack(x_i) * unpack(y_i), x and y packed (n*k bytes each).
+/* result = sum_i unpack(x_i) * unpack(y_i), x and y packed (n*k bytes each):
+ * a BLAS level-1 program of Sections 6.1 and 6.3.1 over k-byte data (Section 3.1).
  * Products and sums in the base type with fma; the reduction order is fixed
  * (per-thread sequential, then fixed trees), so repeated calls on the same
  * device give identical bits.  result: one native value in device memory. */
@@ -114,8 +116,10 @@ fb_status fb_dot(fb_format f, size_t n, const void *x, const void *y, void *resu
 fb_status fb_dot_packed(fb_format f, fb_format fr, size_t n, const void *x, const void *y,
                         void *result, hipStream_t stream);
 
-/* y_i <- pack(fma(alpha, unpack(x_i), unpack(y_i))), in place on y.
- * alpha is first rounded to the native type.  Bit-exact per element.
+/* y_i <- pack(fma(alpha, unpack(x_i), unpack(y_i))), in place on y: a BLAS
+ * level-1 program of Sections 6.1 and 6.3.1, one fused multiply-add in the base type and one
+ * cut (Sections 3.1, 5.2).  alpha is first rounded to the native type.
+ * Bit-exact per element.
  * x and y are packed (n*k bytes); x must not overlap y. */
 fb_status fb_axpy(fb_format f, size_t n, double alpha, const void *x, void *y,
                   hipStream_t stream);
@@ -133,7 +137,9 @@ fb_status fb_nrm2(fb_format f, size_t n, const void *x, void *result, hipStream_
 
 /* ------------------------------------------------------------------ BLAS 2 */
 
-/* y = A x.  A: m x n packed, row-major, leading dimension lda >= n (elements).
+/* y = A x, the BLAS level-2 GEMV of Sections 6.2 and 6.3.2 over a packed A
+ * (codec fused into the loads, Sections 3.2 and 4.1).  A: m x n packed,
+ * row-major, leading dimension lda >= n (elements).
  * x: n native values; y: m native values.  Each y_r is a sequence of fmas in
  * the base type in an order fixed by the tile configuration (chosen by the
  * autotuner cache, else a default for the shape). */
@@ -189,7 +195,8 @@ void fb_tune_clear(void);
 
 /* ------------------------------------------------------------------ batched GEMV */
 
-/* One independent GEMV y = A x of a batch (same semantics as fb_gemv). */
+/* One independent GEMV y = A x of a batch (same semantics as fb_gemv; the
+ * batched schedule itself is not in the paper). */
 typedef struct fb_gemv_desc {
     fb_format f;
     int32_t m;
