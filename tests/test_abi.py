@@ -157,3 +157,34 @@ def test_gemv_config_table():
     infos = [flyte.gemv_config_info(c) for c in range(n)]
     assert all(i["lanes_per_row"] in (8, 16, 32, 64) for i in infos)
     assert flyte.load().fb_gemv_config_info(n, None, None, None) == 0
+
+
+def test_tune_cache_concurrent_threads():
+    """Threads recording and looking up tile choices at once (the foreign calls run without
+    the interpreter lock): every lookup returns a value some thread recorded for that
+    bucket, and the cache ends with one entry per bucket."""
+    import threading
+    flyte.tune_clear()
+    errors = []
+
+    def worker(t):
+        try:
+            for i in range(2000):
+                m = 1 << (4 + (i % 8))
+                flyte.tune_record((64, 3 + (t % 6)), m, 4096, (t + i) % flyte.gemv_num_configs(), 1.0)
+                got = flyte.tune_lookup((64, 3 + (t % 6)), m, 4096)
+                if not (0 <= got < flyte.gemv_num_configs()):
+                    errors.append((t, i, got))
+        except Exception as exc:     # noqa: BLE001 -- collected and reported below
+            errors.append(exc)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(8)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors[:3]
+    for kk in range(3, 9):
+        for e in range(8):
+            assert 0 <= flyte.tune_lookup((64, kk), 1 << (4 + e), 4096) < flyte.gemv_num_configs()
+    flyte.tune_clear()

@@ -121,3 +121,30 @@ def test_gemv_streaming_size_sampled(dev, orc, bench_tiles, k):
     assert check_rows(y[rows], exact, absrow, n, 64).size == 0
     del A
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("f", [(64, 5), (32, 3)])
+def test_tune_gemv_records_a_valid_choice(dev, orc, f):
+    """fb_tune_gemv times every tile on the caller's buffers, records the fastest for the
+    shape bucket and returns it; fb_gemv then uses it, bit-identical to that forced tile,
+    and within the bound against the exact oracle."""
+    import torch
+    base, k = f
+    log(f"tune gemv {f}")
+    m, n = 1536, 2052
+    A = orc.pack(base, k, workloads.uniform(m * n, 31, dtype=native_dtype(base)))
+    x = workloads.uniform(n, 32, dtype=native_dtype(base))
+    Ad, xd = torch.from_numpy(A).to(dev), torch.from_numpy(x).to(dev)
+    flyte.tune_clear()
+    try:
+        y = torch.empty(m, dtype=torch.float32 if base == 32 else torch.float64, device=dev)
+        best = flyte.tune_gemv(f, Ad, m, n, xd, y, reps=2)
+        assert 0 <= best < flyte.gemv_num_configs()
+        assert flyte.tune_lookup(f, m, n) == best
+        auto = flyte.gemv(f, Ad, m, n, xd).cpu().numpy()
+        forced = flyte.gemv(f, Ad, m, n, xd, config=best).cpu().numpy()
+        assert np.array_equal(auto.view(np.uint8), forced.view(np.uint8))
+        exact, absrow = orc.gemv_exact(base, k, m, n, A, n, x)
+        assert check_rows(auto, exact, absrow, n, base).size == 0
+    finally:
+        flyte.tune_clear()
