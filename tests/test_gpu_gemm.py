@@ -274,3 +274,34 @@ def test_gemm_special_values(dev, orc, case):
         bound = gam(K, U64)
     assert np.all(np.isfinite(C[fin]))
     assert np.max(np.abs(C[fin] - ce[fin]) / cab[fin]) <= bound
+
+
+@pytest.mark.parametrize("case", ["bf16", "three", "four", "f64"])
+def test_gemm_padded_leading_dimensions(dev, orc, case):
+    """lda > K, ldb > N, ldc > N (rows padded, still 4-byte aligned): every entry within the
+    bound, and C's padding columns untouched."""
+    import torch
+    M, N, K = 256, 256, 128
+    base, k = (64, 5) if case == "f64" else (32, 2 if case == "bf16" else 3)
+    lda, ldb, ldc = K + 4, N + 8, N + 4
+    g = np.random.default_rng(31)
+    dt = np.float64 if base == 64 else np.float32
+    Av = g.standard_normal((M, lda)).astype(dt)
+    Bv = g.standard_normal((K, ldb)).astype(dt)
+    A, B = orc.pack(base, k, Av.reshape(-1)), orc.pack(base, k, Bv.reshape(-1))
+    if base == 64:
+        fc, cdt, kc = (64, 8), torch.float64, 8
+    else:
+        fc, cdt, kc = (32, 4), torch.float32, 4
+    C = torch.full((M * ldc,), 7.0, dtype=cdt, device=dev)
+    flags = flyte.GEMM_FOUR_PRODUCTS if case == "four" else 0
+    flyte.gemm((base, k), (base, k), fc, M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), C=C,
+               lda=lda, ldb=ldb, ldc=ldc, flags=flags)
+    Ch = C.cpu().numpy().reshape(M, ldc).astype(np.float64)
+    assert np.all(Ch[:, N:] == 7.0)
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((base, k), (base, k), K, A, lda, B, ldb, ii, jj)
+    e1 = np.max(np.abs(Ch[:, :N].reshape(-1) - ce) / cab)
+    bound = {"bf16": gam(K, U32), "three": 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2,
+             "four": gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2, "f64": gam(K, U64)}[case]
+    assert e1 <= bound, (e1, bound)
