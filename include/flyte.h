@@ -48,7 +48,9 @@
  *    fb_dot_packed, fb_nrm2: 16 KiB; transposed fb_gemv_ex: slabs * n native
  *    values; {32,3} fb_gemm: the split operands, (M*K + K*N) * 4 bytes),
  *    allocated on first use on that stream and kept; growing it
- *    synchronises the stream.
+ *    synchronises the stream.  Calls can be captured into a HIP graph; one
+ *    that needs a larger workspace than its stream has returns FB_ERR_RUNTIME
+ *    during capture, so make one call of that size on the stream beforehand.
  *  - Input and output ranges must not overlap unless a call says so.
  */
 #ifndef FLYTE_H

@@ -48,6 +48,14 @@ fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out)
     std::lock_guard<std::mutex> lk(mu);
     auto& slot = cache[std::make_pair(dev, stream)];
     if (slot.second < bytes) {
+        // allocating (or synchronising to release the old buffer) is not allowed
+        // while the stream is being captured into a graph
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
+            return set_error(FB_ERR_RUNTIME,
+                             "workspace: %zu bytes needed while the stream is being captured; make one call of "
+                             "the same size on this stream outside capture first",
+                             bytes);
         size_t want = bytes < 2 * slot.second ? 2 * slot.second : bytes;
         if (want < 16384) want = 16384;
         if (slot.first) {
