@@ -113,6 +113,9 @@ def test_gemm_argument_errors(lib):
                        None) == flyte.FB_OK
     assert lib.fb_gemm_ex(F(32, 2), F(32, 2), F(32, 4), *args[:-1], 1, None) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm_ex(F(32, 3), F(32, 3), F(32, 4), *args[:-1], 4, None) == flyte.FB_ERR_ARG
+    big_n = 65536 * 64     # the split pass of {32,3} B puts N/64 tiles on one grid axis
+    assert lib.fb_gemm(F(32, 3), F(32, 3), F(32, 4), 128, big_n, 64, FAKE, 64, FAKE, big_n, FAKE, big_n,
+                       None) == flyte.FB_ERR_UNSUPPORTED
 
 
 def test_batched_plan_rejects_bad_descriptor(lib):
