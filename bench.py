@@ -11,10 +11,15 @@ vendor FP64 GEMV (torch.mv -> rocBLAS) is timed beside it.
 value = algorithmic bytes of every GEMV in the timed region / wall time.
 Per-k kernel durations come from HIP events on the launch stream; the
 roofline entry reports the GEMV kernels' algorithmic bandwidth against the
-8 TB/s HBM peak.  GEMM throughput (BF16, 3-product, FP64 with a k-byte C) is
-measured after the timed region and reported under "detail".
+8 TB/s HBM peak, with the HBM traffic measured by the committed counter
+profile when it matches the kernels and tiles in use.  After the timed region
+(reported under "detail"): the transposed GEMV, the codec and BLAS-1 kernels
+at 2^28 elements, the batched workload (4096 mixed GEMVs), and the GEMMs (BF16,
+3- and 4-product, FP64 with a k-byte C) with the vendor library's GEMMs beside
+them; cpu_baseline times the oracle's GEMV on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-gemm] [--retune]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--no-gemm] [--no-batched] [--no-blas1] [--retune] [--tune-cache PATH]
 """
 from __future__ import annotations
 
