@@ -43,6 +43,10 @@
  *   4 = unpack shifts by one byte too few (wrong alignment of stored bytes)
  *   5 = sign bit lost on pack
  *   6 = round to odd that never sets the lowest bit (plain truncation)
+ *   7 = the exact accumulator ignores the sign of products
+ *   8 = the transposed GEMV multiplies column c by x in reversed row order
+ *   9 = axpy computes alpha*y + x
+ *  10 = the naive dot rounds each product before adding (no contraction)
  */
 #include <math.h>
 #include <stdint.h>
@@ -259,14 +263,19 @@ void fbo_axpy(int base, int k, size_t n, double alpha, const uint8_t *x, uint8_t
 {
     for (size_t i = 0; i < n; ++i) {
         uint64_t r;
+#if FBO_MUTATION == 9
+        const uint8_t *xa = y, *ya = x;
+#else
+        const uint8_t *xa = x, *ya = y;
+#endif
         if (base == 32) {
             float a = (float)alpha;
-            float xi = (float)elem_value(base, k, x, i);
-            float yi = (float)elem_value(base, k, y, i);
+            float xi = (float)elem_value(base, k, xa, i);
+            float yi = (float)elem_value(base, k, ya, i);
             r = bits_of_float(fmaf(a, xi, yi));
         } else {
-            double xi = elem_value(base, k, x, i);
-            double yi = elem_value(base, k, y, i);
+            double xi = elem_value(base, k, xa, i);
+            double yi = elem_value(base, k, ya, i);
             r = bits_of_double(fma(alpha, xi, yi));
         }
         store_elem(y, k, i, fbo_pack_bits(base, k, r));
@@ -316,7 +325,14 @@ double fbo_dot_naive(int base, int k, size_t n, const uint8_t *x, const uint8_t 
         return (double)s;
     }
     double s = 0.0;
+#if FBO_MUTATION == 10
+    for (size_t i = 0; i < n; ++i) {
+        volatile double p = elem_value(base, k, x, i) * elem_value(base, k, y, i);
+        s = s + p;
+    }
+#else
     for (size_t i = 0; i < n; ++i) s = fma(elem_value(base, k, x, i), elem_value(base, k, y, i), s);
+#endif
     return s;
 }
 
@@ -391,7 +407,13 @@ static void acc_add_product(longacc *a, double x, double y)
     split_double(x, &nx, &mx, &ex);
     split_double(y, &ny, &my, &ey);
     if (mx == 0 || my == 0) return;
+#if FBO_MUTATION == 7
+    (void)nx;
+    (void)ny;
+    acc_add(a, 0, (unsigned __int128)mx * my, ex + ey + ACC_BIAS);
+#else
     acc_add(a, nx != ny, (unsigned __int128)mx * my, ex + ey + ACC_BIAS);
+#endif
 }
 
 static int acc_bit(const uint64_t *v, int i) { return (int)((v[i / 64] >> (i % 64)) & 1); }
@@ -574,7 +596,11 @@ void fbo_gemv_t_exact(int base, int k, int64_t m, int64_t n, const uint8_t *A, i
         acc_init(&b);
         for (int64_t r = 0; r < m; ++r) {
             double av = elem_value(base, k, A + (size_t)r * (size_t)lda * (size_t)k, (size_t)c);
+#if FBO_MUTATION == 8
+            double xv = native_at(x, base, (size_t)(m - 1 - r));
+#else
             double xv = native_at(x, base, (size_t)r);
+#endif
             acc_add_product(&a, av, xv);
             if (abscol) acc_add_product(&b, fabs(av), fabs(xv));
         }

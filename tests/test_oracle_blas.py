@@ -152,6 +152,12 @@ def test_dot_naive_is_sequential_fma(orc):
     # first step: fma(a, a, 0) = RN(1 + 2^-29 + 2^-60) = 1 + 2^-29; then fma(-1, 1+2^-29, that) = 0
     assert orc.dot_naive(64, 8, x, y) == 0.0
     assert orc.dot_exact(64, 8, x, y) == 2.0 ** -60
+    # the other order shows the contraction: fma(-1, 1+2^-29, 0) = -(1+2^-29) exactly, then
+    # fma(a, a, -(1+2^-29)) keeps the 2^-60 of the unrounded product; a separate multiply
+    # and add would round a*a to 1+2^-29 first and return 0
+    x = orc.pack(64, 8, np.array([-1.0, a]))
+    y = orc.pack(64, 8, np.array([1.0 + 2.0 ** -29, a]))
+    assert orc.dot_naive(64, 8, x, y) == 2.0 ** -60
 
 
 @pytest.mark.parametrize("base,k", FORMATS)
@@ -261,3 +267,28 @@ def test_mixed_population_composition():
     assert (bits == np.uint64(0x7FF0000000000001)).any()
     frac_special = 1 - np.isfinite(v).mean()
     assert 0.02 < frac_special < 0.05        # infinities + NaNs are 3 of the 9 special kinds
+
+
+# ---------------------------------------------------------------- planted mistakes in the BLAS references
+BLAS_MUTATIONS = {
+    7: ("exact accumulator ignores the sign of products",
+        [lambda o: test_dot_exact_vs_rational(o, 64, 5), lambda o: test_dot_exact_cancellation_and_tiny(o)]),
+    8: ("transposed GEMV multiplies by the wrong x index",
+        [lambda o: test_gemv_t_exact_vs_rational(o, 64, 3)]),
+    9: ("axpy computes alpha*y + x", [lambda o: test_axpy_vs_rational(o, 32, 3)]),
+    10: ("naive dot rounds each product before adding", [lambda o: test_dot_naive_is_sequential_fma(o)]),
+}
+
+
+@pytest.mark.parametrize("mut", sorted(BLAS_MUTATIONS))
+def test_planted_blas_mutation_is_caught(mut):
+    oracle.build(mut)
+    o = oracle.Oracle(mut)
+    assert o.lib.fbo_mutation() == mut
+    failed = 0
+    for pin in BLAS_MUTATIONS[mut][1]:
+        try:
+            pin(o)
+        except AssertionError:
+            failed += 1
+    assert failed > 0, BLAS_MUTATIONS[mut][0]
