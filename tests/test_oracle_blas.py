@@ -233,15 +233,16 @@ def test_gemv_t_naive_integer_data_and_order(orc):
 def test_gemm_entries_vs_rational(orc):
     g = np.random.default_rng(3)
     M, N, K = 5, 6, 33
+    lda, ldb = K + 3, N + 2      # padded rows: the leading dimensions must be honoured
     for fa in [(32, 2), (32, 3), (64, 5), (64, 6)]:
         base, k = fa
-        Av = (g.standard_normal((M, K)) * np.exp2(g.uniform(-20, 20, (M, K)))).astype(native_dtype(base))
-        Bv = (g.standard_normal((K, N)) * np.exp2(g.uniform(-20, 20, (K, N)))).astype(native_dtype(base))
+        Av = (g.standard_normal((M, lda)) * np.exp2(g.uniform(-20, 20, (M, lda)))).astype(native_dtype(base))
+        Bv = (g.standard_normal((K, ldb)) * np.exp2(g.uniform(-20, 20, (K, ldb)))).astype(native_dtype(base))
         A, B = orc.pack(base, k, Av.reshape(-1)), orc.pack(base, k, Bv.reshape(-1))
         ii, jj = np.array([0, 4, 2]), np.array([5, 0, 3])
-        c, cab = orc.gemm_entries(fa, fa, K, A, K, B, N, ii, jj)
-        Au = orc.unpack(base, k, A).reshape(M, K)
-        Bu = orc.unpack(base, k, B).reshape(K, N)
+        c, cab = orc.gemm_entries(fa, fa, K, A, lda, B, ldb, ii, jj)
+        Au = orc.unpack(base, k, A).reshape(M, lda)
+        Bu = orc.unpack(base, k, B).reshape(K, ldb)
         for t in range(3):
             i, j = ii[t], jj[t]
             terms = [Fraction(float(Au[i, p])) * Fraction(float(Bu[p, j])) for p in range(K)]
