@@ -12,8 +12,9 @@
 // so the result is a fixed sequence of operations for given sizes; the last
 // step writes y native or packed (one rounding, byte stores).  A is streamed
 // once, so units that one load instruction covers (at most 4 dwords) are read
-// non-temporally; 5- and 7-dword units are not, since their two instructions
-// share cache lines.
+// non-temporally.  5- and 7-dword units (two load instructions per unit, which
+// would share cache lines) are read as lane-contiguous row spans and passed
+// through LDS instead, in strips of 64 whole units.
 #include "codec.hpp"
 #include "common.hpp"
 #include "gemv_impl.hpp"
@@ -56,6 +57,45 @@ k_gemv_t(const uint8_t* __restrict__ A, int64_t row_bytes, const void* __restric
     if (g < nunits) {
         const uint8_t* col = A + g * (F::UNIT_DW * 4);
         int r = r0 + w * U;
+        if constexpr (F::UNIT_DW > 4) {
+            // 5- and 7-dword units: a full strip's span of each row (64 units) is read
+            // with two lane-contiguous non-temporal loads (the first KiB as dwordx4, the
+            // rest as one more piece per lane), passed through the wave's LDS row buffer,
+            // and each lane reads its own unit back (odd dword stride: no bank conflicts)
+            if (((int64_t)blockIdx.x + 1) * 64 <= nunits) {
+                constexpr int SPAN = 64 * F::UNIT_DW;   // dwords of one row of the strip
+                constexpr int REST = F::UNIT_DW - 4;    // dwords per lane after the first KiB
+                __shared__ __attribute__((aligned(16))) uint32_t stage[kGtWaves][SPAN];
+                const uint8_t* strip = A + (int64_t)blockIdx.x * SPAN * 4;
+                for (; r + U <= r1; r += kGtWaves * U) {
+                    uint32_t L[U][4], Q[U][REST];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const uint32_t* rp = reinterpret_cast<const uint32_t*>(strip + (int64_t)(r + u) * row_bytes);
+                        load_dwords_nt(rp + lane * 4, L[u]);
+                        load_dwords_nt(rp + 256 + lane * REST, Q[u]);
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        *reinterpret_cast<u32x4*>(&stage[w][lane * 4]) = u32x4{L[u][0], L[u][1], L[u][2], L[u][3]};
+#pragma unroll
+                        for (int j = 0; j < REST; ++j) stage[w][256 + lane * REST + j] = Q[u][j];
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        uint32_t P[F::UNIT_DW];
+#pragma unroll
+                        for (int j = 0; j < F::UNIT_DW; ++j) P[j] = stage[w][lane * F::UNIT_DW + j];
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        T ab[F::UNIT];
+                        unpack_elems<F, F::UNIT>(P, ab);
+                        const N xr = x[r + u];
+#pragma unroll
+                        for (int e = 0; e < F::UNIT; ++e) acc[e] = fma_n(as_native<F>(ab[e]), xr, acc[e]);
+                    }
+                }
+            }
+        }
         for (; r + U <= r1; r += kGtWaves * U) {
             uint32_t P[U][F::UNIT_DW];
 #pragma unroll
