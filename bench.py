@@ -363,8 +363,10 @@ def bench_blas1(flyte, workloads, torch, dev, stream):
     nat = torch.empty(n, dtype=torch.float64, device=dev).uniform_(-1.0, 1.0, generator=g)
     out = {"n": n}
 
-    def timed(fn, reps=3):
-        fn()
+    def timed(fn, reps=3, warm=3):
+        # untimed calls first (the GPU may have idled during the host-side steps before)
+        for _ in range(warm):
+            fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
