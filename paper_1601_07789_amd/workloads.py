@@ -139,6 +139,12 @@ def normal(shape, seed: int, dtype=np.float32) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)
 
 
+def small_integers(n: int, seed: int, dtype=np.float64, lo: int = -8, hi: int = 8) -> np.ndarray:
+    """Integers in [lo, hi] as floating point: exact in every format with at least
+    four kept mantissa bits, and their products and sums stay exact in binary64."""
+    return np.random.default_rng(seed).integers(lo, hi + 1, n).astype(dtype)
+
+
 def group_elems(k: int) -> int:
     """Elements per dword-aligned group: 4 / gcd(4, k)."""
     from math import gcd

@@ -1,0 +1,135 @@
+"""Sizes past 32-bit indexing: more than 2^31 elements, or more than 4 GiB in one
+buffer, for pack, unpack, axpy, dot and both GEMV orders.
+
+Each large operand is a small block repeated on the device (a plain tensor
+repeat; the last copy is cut, so the tails are ragged).  The blocks are packed by
+the oracle, so each expected result is the oracle's result for the block, tiled
+the same way, or, for the reductions, an exact integer sum: with small-integer
+data every product and partial sum is exact in binary64, so the result is the
+same in any summation order and is checked bit for bit.
+"""
+from __future__ import annotations
+
+import gc
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import device, log, mixed
+from paper_1601_07789_amd import flyte, workloads
+
+pytestmark = pytest.mark.gpu
+
+PAST_2_31 = (1 << 31) + 3 * 4096 + 5      # elements
+BLOCK = 1 << 16                           # elements per repeated block
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.default()
+
+
+@pytest.fixture(autouse=True)
+def _free_memory():
+    yield
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def tile(block, total):
+    """The 1-D device tensor `block` repeated to `total` elements."""
+    reps = -(-total // block.numel())
+    return block.repeat(reps)[:total]
+
+
+def same_bits(a, b):
+    import torch
+    return a.numel() == b.numel() and bool(torch.equal(a.view(torch.uint8), b.view(torch.uint8)))
+
+
+@pytest.mark.parametrize("f,n", [((32, 2), PAST_2_31), ((64, 5), (1 << 30) + 3)])
+def test_pack_unpack_past_32_bits(dev, orc, f, n):
+    import torch
+    base, k = f
+    log(f"pack/unpack {f} n={n} ({n * k / 2**30:.2f} GiB packed)")
+    nat = np.float32 if base == 32 else np.float64
+    block = mixed(base, BLOCK, 4000).view(nat)
+    exp_packed = torch.from_numpy(orc.pack(base, k, block)).to(dev)
+    exp_native = torch.from_numpy(orc.unpack(base, k, orc.pack(base, k, block), BLOCK)).to(dev)
+    src = tile(torch.from_numpy(block).to(dev), n)
+    packed = flyte.pack(f, src)
+    del src
+    assert same_bits(packed, tile(exp_packed, n * k))
+    out = flyte.unpack(f, packed, n=n)
+    del packed
+    assert same_bits(out, tile(exp_native, n))
+
+
+def test_axpy_past_2_31(dev, orc):
+    import torch
+    f, n, alpha = (64, 3), PAST_2_31, float.fromhex("0x1.5555555555555p-2")
+    log(f"axpy {f} n={n}")
+    xb = orc.pack(64, 3, workloads.uniform(BLOCK, 4010))
+    yb = orc.pack(64, 3, workloads.uniform(BLOCK, 4011))
+    exp = torch.from_numpy(orc.axpy(64, 3, alpha, xb, yb)).to(dev)
+    x = tile(torch.from_numpy(xb).to(dev), 3 * n)
+    y = tile(torch.from_numpy(yb).to(dev), 3 * n).clone()
+    flyte.axpy(f, alpha, x, y, n=n)
+    assert same_bits(y, tile(exp, 3 * n))
+
+
+def test_dot_past_2_31_exact(dev, orc):
+    import torch
+    f, n = (64, 3), PAST_2_31
+    log(f"dot {f} n={n}")
+    xv = workloads.small_integers(BLOCK, 4020)
+    yv = workloads.small_integers(BLOCK, 4021)
+    xb, yb = orc.pack(64, 3, xv), orc.pack(64, 3, yv)
+    assert np.array_equal(orc.unpack(64, 3, xb, BLOCK), xv)        # the integers are kept exactly
+    prod = xv.astype(np.int64) * yv.astype(np.int64)
+    full, rest = divmod(n, BLOCK)
+    exact = full * int(prod.sum()) + int(prod[:rest].sum())
+    x = tile(torch.from_numpy(xb).to(dev), 3 * n)
+    y = tile(torch.from_numpy(yb).to(dev), 3 * n)
+    got = flyte.dot(f, x, y, n=n).item()
+    assert got == float(exact), (got, exact)
+
+
+@pytest.mark.parametrize("f,m", [((64, 8), 64 * 1040), ((64, 5), 64 * 1664)])
+def test_gemv_past_4gib_exact(dev, orc, f, m):
+    import torch
+    base, k = f
+    n = 8192
+    assert m * n * k > (1 << 32)
+    log(f"gemv {f} {m}x{n} ({m * n * k / 2**30:.2f} GiB)")
+    Ab = workloads.small_integers(64 * n, 4030)
+    xv = workloads.small_integers(n, 4031)
+    Apk = orc.pack(base, k, Ab)
+    yb = Ab.reshape(64, n).astype(np.int64) @ xv.astype(np.int64)
+    A = tile(torch.from_numpy(Apk).to(dev), m * n * k)
+    y = flyte.gemv(f, A, m, n, torch.from_numpy(xv).to(dev))
+    exp = tile(torch.from_numpy(yb.astype(np.float64)).to(dev), m)
+    assert same_bits(y, exp)
+
+
+def test_gemv_transposed_past_4gib_exact(dev, orc):
+    import torch
+    f, n, reps = (64, 3), 8192, 2731
+    m = 64 * reps
+    assert m * n * 3 > (1 << 32)
+    log(f"transposed gemv {f} {m}x{n} ({m * n * 3 / 2**30:.2f} GiB)")
+    Ab = workloads.small_integers(64 * n, 4040)
+    xb = workloads.small_integers(64, 4041)
+    Apk = orc.pack(64, 3, Ab)
+    yt = reps * (Ab.reshape(64, n).astype(np.int64).T @ xb.astype(np.int64))
+    A = tile(torch.from_numpy(Apk).to(dev), m * n * 3)
+    x = tile(torch.from_numpy(xb).to(dev), m)
+    y = flyte.gemv_ex(f, (64, 8), True, A, m, n, x)
+    assert same_bits(y, torch.from_numpy(yt.astype(np.float64)).to(dev))
