@@ -133,3 +133,31 @@ def test_gemv_transposed_past_4gib_exact(dev, orc):
     x = tile(torch.from_numpy(xb).to(dev), m)
     y = flyte.gemv_ex(f, (64, 8), True, A, m, n, x)
     assert same_bits(y, torch.from_numpy(yt.astype(np.float64)).to(dev))
+
+
+@pytest.mark.parametrize("f,size", [((32, 2), 49152), ((32, 3), 49152), ((64, 5), 32768)])
+def test_gemm_past_4gib_exact(dev, orc, f, size):
+    """A and B (more than 4 GiB each) repeat 64 x 64 and 64 x N integer blocks, so C
+    repeats a 64 x N block of integers that every product and partial sum represents
+    exactly: C must equal it bit for bit (for a packed C, the oracle's pack of it)."""
+    import torch
+    base, k = f
+    M = N = K = size
+    assert M * K * k > (1 << 32)
+    log(f"gemm {f} {M}^3 ({M * K * k / 2**30:.2f} GiB per operand)")
+    nat = np.float32 if base == 32 else np.float64
+    Abb = workloads.small_integers(64 * 64, 4050, dtype=nat).reshape(64, 64)
+    Bb = workloads.small_integers(64 * N, 4051, dtype=nat).reshape(64, N)
+    reps = K // 64
+    Cb = reps * (Abb.astype(np.int64) @ Bb.astype(np.int64))           # 64 x N block of C
+    A = torch.from_numpy(orc.pack(base, k, Abb.reshape(-1))).to(dev).view(64, 64 * k).repeat(M // 64, reps).reshape(-1)
+    B = torch.from_numpy(orc.pack(base, k, Bb.reshape(-1))).to(dev).view(64, N * k).repeat(reps, 1).reshape(-1)
+    if base == 32:
+        C = flyte.gemm(f, f, (32, 4), M, N, K, A, B)
+        exp = torch.from_numpy(Cb.astype(np.float32)).to(dev).repeat(M // 64, 1).reshape(-1)
+    else:
+        C = flyte.gemm(f, f, f, M, N, K, A, B)
+        exp = torch.from_numpy(orc.pack(64, k, Cb.astype(np.float64).reshape(-1))).to(dev)
+        exp = exp.view(64, N * k).repeat(M // 64, 1).reshape(-1)
+    del A, B
+    assert same_bits(C, exp)
