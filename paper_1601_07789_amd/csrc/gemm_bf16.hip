@@ -23,10 +23,11 @@
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
 // wave tiles keep LDS operand traffic below the LDS bandwidth (a 64 x 128 or
 // 128 x 64 wave tile reads about 94 B/clk of LDS per CU at the MFMA peak,
-// against 128 available).  256 x 256 x 32 tiles with 8 waves: BF16 as 4 x 2
-// waves of 64 x 128, the split products as 2 x 4 waves of 128 x 64 (their two
-// planes fill the 160 KiB of LDS exactly); the short K step keeps registers
-// for two waves per SIMD.  Shapes that are not multiples of 256 use 256 x 128
+// against 128 available).  8 waves per workgroup, two per SIMD: BF16 in
+// 256 x 256 x 64 tiles as 4 x 2 waves of 64 x 128 (144 KiB of LDS), the split
+// products in 256 x 256 x 32 tiles as 2 x 4 waves of 128 x 64 (their two
+// planes fill the 160 KiB of LDS exactly; the short K step keeps registers
+// for two waves per SIMD).  Shapes that are not multiples of 256 use 256 x 128
 // x 32 (split products, M a multiple of 256) or 128 x 128 x 64.  K is
 // walked in BK steps through double-buffered LDS (one barrier per step; the
 // next step's global loads are issued before the current step's MFMAs; the
@@ -232,16 +233,33 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
 #pragma unroll
             for (int i = 0; i < FM; ++i)
                 a[i] = *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                b[j] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
             if constexpr (MODE == 0) {
+                // B fragments are read one column block ahead of the MFMAs that
+                // use them, so the wave waits for one LDS read at a time instead
+                // of all of them before its first MFMA (the group barriers keep
+                // the compiler to this order: A and two B reads, then one B read
+                // per FM MFMAs)
+                b[0] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + r16) * ROW + ks * 32 + kq);
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                for (int j = 0; j < FN; ++j) {
+                    if (j + 1 < FN)
+                        b[j + 1] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + (j + 1) * 16 + r16) * ROW +
+                                                                     ks * 32 + kq);
 #pragma unroll
-                    for (int j = 0; j < FN; ++j)
+                    for (int i = 0; i < FM; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                }
+                __builtin_amdgcn_sched_group_barrier(0x100, FM + 1, 0);   // LDS reads
+#pragma unroll
+                for (int j = 0; j + 1 < FN; ++j) {
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);   // MFMAs
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);
             } else {
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    b[j] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
                 const uint16_t* Al = a_tile(s, 1);
                 const uint16_t* Bl = b_tile(s, 1);
                 bf16x8_t al[FM], bl[FN];
@@ -382,7 +400,7 @@ fb_status gemm_bf16_launch(int mode, int64_t M, int64_t N, int64_t K, const void
         return set_error(FB_ERR_UNSUPPORTED, "fb_gemm: {32,3} operands need N <= %d", 65535 * 64);
     if (mode == 0) {
         if (M % 256 == 0 && N % 256 == 0)
-            launch_b32<0, 256, 256, 32, 4, 2, 4>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+            launch_b32<0, 256, 256, 64, 4, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
         else
             launch_b32<0, 128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     } else {
