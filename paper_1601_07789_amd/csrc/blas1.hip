@@ -15,6 +15,49 @@
 
 namespace flyte {
 
+// Streaming loads and stores: every byte is touched once, so a lane's unit
+// that one instruction covers (at most 4 dwords: the wave's instruction spans
+// one contiguous range) goes through the non-temporal path; units of more
+// dwords take two instructions whose spans interleave by lane, and stay on the
+// ordinary path (non-temporal there measured slower, as low as 0.75x).
+template <int N>
+__device__ __forceinline__ void load_stream(const uint32_t* __restrict__ p, uint32_t (&out)[N])
+{
+    if constexpr (N == 4) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+        out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else if constexpr (N == 3) {
+        const u32x3 v = __builtin_nontemporal_load(reinterpret_cast<const u32x3*>(p));
+        out[0] = v.x; out[1] = v.y; out[2] = v.z;
+    } else if constexpr (N == 2) {
+        const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+        out[0] = v.x; out[1] = v.y;
+    } else if constexpr (N == 1) {
+        out[0] = __builtin_nontemporal_load(p);
+    } else {
+        load_dwords(p, out);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void store_stream(uint32_t* __restrict__ p, const uint32_t (&in)[N])
+{
+    if constexpr (N == 4) {
+        u32x4 v; v.x = in[0]; v.y = in[1]; v.z = in[2]; v.w = in[3];
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p));
+    } else if constexpr (N == 3) {
+        u32x3 v; v.x = in[0]; v.y = in[1]; v.z = in[2];
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x3*>(p));
+    } else if constexpr (N == 2) {
+        u32x2 v; v.x = in[0]; v.y = in[1];
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p));
+    } else if constexpr (N == 1) {
+        __builtin_nontemporal_store(in[0], p);
+    } else {
+        store_dwords(p, in);
+    }
+}
+
 constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
@@ -31,7 +74,7 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_dwords(src + g * F::UNIT_NW, w[u]);
+            if (g < nunits) load_stream(src + g * F::UNIT_NW, w[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
@@ -43,7 +86,7 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
                 for (int e = 0; e < F::UNIT; ++e) b[e] = round_pack<F, MODE>(b[e]);
                 uint32_t P[F::UNIT_DW];
                 assemble_elems<F, F::UNIT>(b, P);
-                store_dwords(dst + g * F::UNIT_DW, P);
+                store_stream(dst + g * F::UNIT_DW, P);
             }
         });
     }
@@ -71,7 +114,7 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_dwords(src + g * (NE * F::k / 4), P[u]);
+            if (g < nunits) load_stream(src + g * (NE * F::k / 4), P[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
@@ -81,7 +124,7 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
                 unpack_elems<F, NE>(P[u], b);
                 uint32_t w[(NE * F::W / 4)];
                 bits_to_words<F, NE>(b, w);
-                store_dwords(dst + g * (NE * F::W / 4), w);
+                store_stream(dst + g * (NE * F::W / 4), w);
             }
         });
     }
@@ -114,8 +157,8 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
             if (g < nunits) {
-                load_dwords(x + g * F::UNIT_DW, PX[u]);
-                load_dwords(y + g * F::UNIT_DW, PY[u]);
+                load_stream(x + g * F::UNIT_DW, PX[u]);
+                load_stream(y + g * F::UNIT_DW, PY[u]);
             }
         });
         static_for<U>([&](auto iu) {
@@ -130,7 +173,7 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
                     by[e] = round_pack<F, MODE>(as_bits<F>(fma_n(alpha, as_native<F>(bx[e]), as_native<F>(by[e]))));
                 uint32_t P[F::UNIT_DW];
                 assemble_elems<F, F::UNIT>(by, P);
-                store_dwords(y + g * F::UNIT_DW, P);
+                store_stream(y + g * F::UNIT_DW, P);
             }
         });
     }
@@ -159,7 +202,7 @@ k_scale(typename F::native_t alpha, uint32_t* __restrict__ x, int64_t nunits, in
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_dwords(x + g * F::UNIT_DW, PX[u]);
+            if (g < nunits) load_stream(x + g * F::UNIT_DW, PX[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
@@ -171,7 +214,7 @@ k_scale(typename F::native_t alpha, uint32_t* __restrict__ x, int64_t nunits, in
                 for (int e = 0; e < F::UNIT; ++e) bx[e] = round_pack<F, MODE>(as_bits<F>(alpha * as_native<F>(bx[e])));
                 uint32_t P[F::UNIT_DW];
                 assemble_elems<F, F::UNIT>(bx, P);
-                store_dwords(x + g * F::UNIT_DW, P);
+                store_stream(x + g * F::UNIT_DW, P);
             }
         });
     }
@@ -208,7 +251,8 @@ __device__ __forceinline__ T block_sum(T v)
     return s;
 }
 
-template <class F, int U>
+// SQ: y is x (the sum of squares of fb_nrm2), read once.
+template <class F, int U, bool SQ = false>
 __global__ void __launch_bounds__(kBlock)
 k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, int64_t nunits, int64_t n,
               typename F::native_t* __restrict__ partials)
@@ -224,8 +268,8 @@ k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, in
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
             if (g < nunits) {
-                load_dwords(x + g * F::UNIT_DW, PX[u]);
-                load_dwords(y + g * F::UNIT_DW, PY[u]);
+                load_stream(x + g * F::UNIT_DW, PX[u]);
+                if constexpr (!SQ) load_stream(y + g * F::UNIT_DW, PY[u]);
             }
         });
         static_for<U>([&](auto iu) {
@@ -234,7 +278,8 @@ k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, in
             if (g < nunits) {
                 T bx[F::UNIT], by[F::UNIT];
                 unpack_elems<F, F::UNIT>(PX[u], bx);
-                unpack_elems<F, F::UNIT>(PY[u], by);
+                if constexpr (SQ) unpack_elems<F, F::UNIT>(PX[u], by);
+                else unpack_elems<F, F::UNIT>(PY[u], by);
 #pragma unroll
                 for (int e = 0; e < F::UNIT; ++e) acc = fma_n(as_native<F>(bx[e]), as_native<F>(by[e]), acc);
             }
@@ -442,9 +487,9 @@ extern "C" fb_status fb_nrm2(fb_format f, size_t n, const void* x, void* result,
         const int64_t nunits = (int64_t)(n / F::UNIT);
         int grid = stream_grid(nunits, kUnroll);
         if (grid > kMaxDotBlocks) grid = kMaxDotBlocks;
-        k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
-                                                               static_cast<const uint32_t*>(x), nunits,
-                                                               (int64_t)n, static_cast<N*>(ws));
+        k_dot_partial<F, kUnroll, true><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
+                                                                     static_cast<const uint32_t*>(x), nunits,
+                                                                     (int64_t)n, static_cast<N*>(ws));
         k_dot_final<N, true><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
         return check_launch("fb_nrm2");
     });
