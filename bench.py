@@ -16,7 +16,9 @@ profile when it matches the kernels and tiles in use.  After the timed region
 (reported under "detail"): the transposed GEMV, the codec and BLAS-1 kernels
 at 2^28 elements, the batched workload (4096 mixed GEMVs), and the GEMMs (BF16,
 3- and 4-product, FP64 with a k-byte C) with the vendor library's GEMMs beside
-them; cpu_baseline times the oracle's GEMV on the host.
+them; cpu_baseline times the oracle's GEMV on the host.  detail.provenance names
+the input seeds, the git commit (when the tree is a repository) and a hash of
+the kernel sources.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                        [--no-gemm] [--no-batched] [--no-blas1] [--retune] [--tune-cache PATH]
@@ -69,6 +71,8 @@ def main() -> int:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1).", file=sys.stderr)
         return 2
+
+    prov = provenance()      # before the device is touched (it may start git as a child)
 
     import numpy as np
     import torch
@@ -240,6 +244,11 @@ def main() -> int:
         except Exception as e:
             detail["batched"] = {"error": f"{type(e).__name__}: {e}"}
 
+    prov["seeds"] = {"gemv_A": workloads.SEED_BASE + 1, "gemv_x": workloads.SEED_BASE + 101,
+                     "gemm_b32": workloads.SEED_BASE + 2, "batched": workloads.SEED_BASE + 3,
+                     "gemm_f64": workloads.SEED_BASE + 4, "blas1": workloads.SEED_BASE + 1}
+    detail["provenance"] = prov
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -254,6 +263,30 @@ def main() -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def provenance() -> dict:
+    """The git commit of the tree (None where the tree carries no repository) and a
+    sha256 prefix over the kernel sources and the C header, so a result line names
+    the code it measured."""
+    import hashlib
+    import subprocess
+    commit = None
+    try:
+        r = subprocess.run(["git", "rev-parse", "--show-toplevel", "HEAD"], cwd=ROOT, capture_output=True,
+                           text=True, timeout=20)
+        out = r.stdout.split()
+        # only this tree's own repository (a parent directory's would name other code)
+        if r.returncode == 0 and len(out) == 2 and os.path.realpath(out[0]) == os.path.realpath(ROOT):
+            commit = out[1]
+    except (OSError, subprocess.SubprocessError):
+        pass
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1601_07789_amd", "csrc")
+    for f in sorted(os.listdir(csrc)) + ["../../include/flyte.h"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return {"git_commit": commit, "sources_sha256": h.hexdigest()[:16]}
 
 
 def source_hash() -> str:

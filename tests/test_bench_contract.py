@@ -5,6 +5,7 @@
 * The committed HBM-counter summary of the GEMV matches the current GEMV sources
   and the committed tile cache, so the benchmark reports measured traffic rather
   than null (a changed GEMV kernel or tile choice needs new counter passes).
+* The provenance entry names this repository's commit and a source hash.
 """
 from __future__ import annotations
 
@@ -45,3 +46,12 @@ def test_counter_summary_matches_sources_and_tiles():
     assert traffic is not None, "profiles/gemv_8192x8192_k3-8_hbm_counters.md is stale"
     algorithmic = sum(bench.gemv_bytes(k) for k in bench.KS)
     assert 0.99 * algorithmic <= traffic <= 1.05 * algorithmic
+
+
+def test_provenance_names_this_tree():
+    bench = load_bench()
+    p = bench.provenance()
+    assert len(p["sources_sha256"]) == 16
+    r = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True)
+    if r.returncode == 0:
+        assert p["git_commit"] == r.stdout.strip()
