@@ -52,6 +52,9 @@ def test_provenance_names_this_tree():
     bench = load_bench()
     p = bench.provenance()
     assert len(p["sources_sha256"]) == 16
-    r = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True)
-    if r.returncode == 0:
-        assert p["git_commit"] == r.stdout.strip()
+    r = subprocess.run(["git", "rev-parse", "--show-toplevel", "HEAD"], cwd=ROOT, capture_output=True, text=True)
+    out = r.stdout.split()
+    if r.returncode == 0 and len(out) == 2 and os.path.realpath(out[0]) == os.path.realpath(ROOT):
+        assert p["git_commit"] == out[1]
+    else:
+        assert p["git_commit"] is None
