@@ -227,42 +227,63 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         const uint16_t* Ah = a_tile(s, 0);
         const uint16_t* Bh = b_tile(s, 0);
         const int r16 = lane % 16, kq = 8 * (lane / 16);
+        if constexpr (MODE == 0) {
+            // One read-ahead pipeline over the K sub-steps of the stage: each B
+            // fragment is read one column block ahead of the MFMAs that use it
+            // (the last block reads the next sub-step's first B fragment), and
+            // the next sub-step's A fragments are read halfway through the
+            // current one, so the wave waits for at most one LDS read before an
+            // MFMA group.  The group barriers keep the compiler to this order.
+            constexpr int KSN = BK / 32, JA = FN / 2;
+            auto read_a = [&](int ks, int i) {
+                return *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
+            };
+            auto read_b = [&](int ks, int j) {
+                return *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
+            };
+            bf16x8_t a[2][FM], b[FN];
 #pragma unroll
-        for (int ks = 0; ks < BK / 32; ++ks) {
-            bf16x8_t a[FM], b[FN];
+            for (int i = 0; i < FM; ++i) a[0][i] = read_a(0, i);
+            b[0] = read_b(0, 0);
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[i] = *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
-            if constexpr (MODE == 0) {
-                // B fragments are read one column block ahead of the MFMAs that
-                // use them, so the wave waits for one LDS read at a time instead
-                // of all of them before its first MFMA (the group barriers keep
-                // the compiler to this order: A and two B reads, then one B read
-                // per FM MFMAs)
-                b[0] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + r16) * ROW + ks * 32 + kq);
+            for (int ks = 0; ks < KSN; ++ks) {
 #pragma unroll
                 for (int j = 0; j < FN; ++j) {
-                    if (j + 1 < FN)
-                        b[j + 1] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + (j + 1) * 16 + r16) * ROW +
-                                                                     ks * 32 + kq);
+                    if (j + 1 < FN) b[j + 1] = read_b(ks, j + 1);
+                    else if (ks + 1 < KSN) b[0] = read_b(ks + 1, 0);
+                    if (j == JA && ks + 1 < KSN) {
+#pragma unroll
+                        for (int i = 0; i < FM; ++i) a[(ks + 1) & 1][i] = read_a(ks + 1, i);
+                    }
 #pragma unroll
                     for (int i = 0; i < FM; ++i)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks & 1][i], b[j], acc[i][j], 0, 0, 0);
                 }
-                __builtin_amdgcn_sched_group_barrier(0x100, FM + 1, 0);   // LDS reads
+            }
+            __builtin_amdgcn_sched_group_barrier(0x100, FM + 1, 0);   // LDS reads
 #pragma unroll
-                for (int j = 0; j + 1 < FN; ++j) {
-                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            for (int ks = 0; ks < KSN; ++ks) {
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    if (ks < KSN - 1 || j < FN - 1) {
+                        if (j == JA && ks + 1 < KSN) __builtin_amdgcn_sched_group_barrier(0x100, 1 + FM, 0);
+                        else __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
                     __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);   // MFMAs
                 }
-                __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);
-            } else {
+            }
+        } else {
+            const uint16_t* Al = a_tile(s, 1);
+            const uint16_t* Bl = b_tile(s, 1);
+#pragma unroll
+            for (int ks = 0; ks < BK / 32; ++ks) {
+                bf16x8_t a[FM], b[FN], al[FM], bl[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    a[i] = *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     b[j] = *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
-                const uint16_t* Al = a_tile(s, 1);
-                const uint16_t* Bl = b_tile(s, 1);
-                bf16x8_t al[FM], bl[FN];
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
                     al[i] = *reinterpret_cast<const bf16x8_t*>(Al + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
