@@ -88,7 +88,7 @@ def test_gemv_transposed_empty(dev):
     flyte.gemv_ex((64, 8), (64, 8), True, A, 3, 0, x, y=y, lda=0)     # n = 0: nothing
 
 
-@pytest.mark.parametrize("k", [3, 5, 7, 8])
+@pytest.mark.parametrize("k", [3, 4, 5, 7, 8])
 def test_gemv_transposed_streaming_size_sampled(dev, orc, k):
     import torch
     log(f"gemv transposed 8192^2 k={k}")
