@@ -107,6 +107,14 @@ __global__ void __launch_bounds__(kBlock)
 k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
 {
     using T = typename F::bits_t;
+    constexpr int OW = NE * F::W / 4;    // output dwords per lane unit
+    // A unit of 8 output dwords (four binary64 values, odd k) takes two store
+    // instructions whose spans interleave by lane; when all 64 units of a wave
+    // are in range they go through the wave's LDS slice and leave as two
+    // lane-contiguous KiB (non-temporal) instead.
+    constexpr bool STAGE = OW == 8;
+    __shared__ __attribute__((aligned(16))) uint32_t stage[STAGE ? kBlock / 64 : 1][STAGE ? 64 * OW : 4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
@@ -119,12 +127,33 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            uint32_t w[OW];
             if (g < nunits) {
                 T b[NE];
                 unpack_elems<F, NE>(P[u], b);
-                uint32_t w[(NE * F::W / 4)];
                 bits_to_words<F, NE>(b, w);
-                store_stream(dst + g * (NE * F::W / 4), w);
+            }
+            if constexpr (STAGE) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    *reinterpret_cast<u32x4*>(&stage[wave][lane * 8]) = u32x4{w[0], w[1], w[2], w[3]};
+                    *reinterpret_cast<u32x4*>(&stage[wave][lane * 8 + 4]) = u32x4{w[4], w[5], w[6], w[7]};
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    uint32_t v0[4], v1[4];
+                    const u32x4 a = *reinterpret_cast<const u32x4*>(&stage[wave][lane * 4]);
+                    const u32x4 c = *reinterpret_cast<const u32x4*>(&stage[wave][256 + lane * 4]);
+                    v0[0] = a.x; v0[1] = a.y; v0[2] = a.z; v0[3] = a.w;
+                    v1[0] = c.x; v1[1] = c.y; v1[2] = c.z; v1[3] = c.w;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    store_stream(dst + gw * OW + lane * 4, v0);
+                    store_stream(dst + gw * OW + 256 + lane * 4, v1);
+                } else if (g < nunits) {
+                    store_stream(dst + g * OW, w);
+                }
+            } else if (g < nunits) {
+                store_stream(dst + g * OW, w);
             }
         });
     }
