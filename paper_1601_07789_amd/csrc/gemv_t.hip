@@ -23,14 +23,24 @@ namespace flyte {
 
 constexpr int kGtBlock = 256;
 constexpr int kGtWaves = kGtBlock / 64;
-// Rows per chunk (loads in flight per lane): 8, or 16 for the binary64 4- and
-// 5-byte formats (measured on 8192 x 8192: +2-3% there, -10% at 3 bytes).
+constexpr int kGtTarget = 1024;     // workgroups to aim for (strips x slabs), see gt_target
+
+// Rows per chunk (loads in flight per lane) and workgroups to aim for, per
+// format, as measured on 8192 x 8192: 8 rows and 1024 workgroups, except 12
+// rows for binary64 k = 4 (+2-3%), 16 for k = 5 (+2-3%) and 768 workgroups for
+// k = 8 (+3%); each of these lost elsewhere (16 rows: -10% at k = 3; 768
+// workgroups: -10% at k = 3, -1% at k = 6).
 template <class F>
 constexpr int gt_rows()
 {
-    return (F::base == 64 && (F::k == 4 || F::k == 5)) ? 16 : 8;
+    return F::base == 64 && F::k == 4 ? 12 : (F::base == 64 && F::k == 5 ? 16 : 8);
 }
-constexpr int kGtTarget = 1024;     // workgroups to aim for (strips x slabs)
+
+template <class F>
+constexpr int64_t gt_target()
+{
+    return F::base == 64 && F::k == 8 ? 768 : kGtTarget;
+}
 
 template <class F>
 __device__ __forceinline__ void gemv_t_store(typename F::native_t v, int64_t c, typename F::native_t* partial,
@@ -209,7 +219,7 @@ fb_status gemv_t_launch(fb_format fa, fb_format fy, int64_t m, int64_t n, const 
         const int64_t nstrips = (ncolunits + 63) / 64;
         constexpr int U = gt_rows<F>();
         constexpr int64_t kChunkRows = (int64_t)kGtWaves * U;     // one chunk per wave
-        int64_t nslabs = (kGtTarget + nstrips - 1) / nstrips;
+        int64_t nslabs = (gt_target<F>() + nstrips - 1) / nstrips;
         const int64_t max_slabs = (m + 2 * kChunkRows - 1) / (2 * kChunkRows);   // >= 2 chunks per wave
         if (nslabs > max_slabs) nslabs = max_slabs;
         if (nslabs < 1) nslabs = 1;
