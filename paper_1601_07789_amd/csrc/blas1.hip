@@ -58,6 +58,43 @@ __device__ __forceinline__ void store_stream(uint32_t* __restrict__ p, const uin
     }
 }
 
+
+// Wave-cooperative reads of 64 consecutive lane units of D dwords, D = 5 or 7
+// (units a lane alone would read with two instructions whose spans interleave
+// by lane): the wave reads the 64 D dwords as lane-contiguous 16-byte chunks,
+// non-temporal (span_load), then passes them through its LDS slice so each
+// lane gets its own unit (span_unit).  All 64 lanes must be active and the
+// whole span in range; base is 16-byte aligned when the array is (a wave's
+// first unit is a multiple of 64).
+template <int D>
+struct SpanChunks {
+    u32x4 c0, c1;
+};
+
+template <int D>
+__device__ __forceinline__ SpanChunks<D> span_load(const uint32_t* __restrict__ base, int lane)
+{
+    constexpr int CH = 64 * D / 4;   // 16-byte chunks of the span: 80 or 112
+    SpanChunks<D> c;
+    c.c0 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + lane);
+    if (64 + lane < CH) c.c1 = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base) + 64 + lane);
+    return c;
+}
+
+template <int D>
+__device__ __forceinline__ void span_unit(uint32_t* slice, int lane, const SpanChunks<D>& c, uint32_t (&out)[D])
+{
+    constexpr int CH = 64 * D / 4;
+    *reinterpret_cast<u32x4*>(slice + 4 * lane) = c.c0;
+    if (64 + lane < CH) *reinterpret_cast<u32x4*>(slice + 4 * (64 + lane)) = c.c1;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int j = 0; j < D; ++j) out[j] = slice[D * lane + j];   // odd stride: no bank conflicts
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
@@ -288,22 +325,41 @@ k_dot_partial(const uint32_t* __restrict__ x, const uint32_t* __restrict__ y, in
 {
     using T = typename F::bits_t;
     using N = typename F::native_t;
+    constexpr int D = F::UNIT_DW;
+    constexpr bool STG = D == 5 || D == 7;   // two-instruction units: read as wave spans
+    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][2][STG ? 64 * D : 4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     N acc = N(0);
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
-        uint32_t PX[U][F::UNIT_DW], PY[U][F::UNIT_DW];
+        uint32_t PX[U][D], PY[U][D];
+        SpanChunks<D> SX[STG ? U : 1], SY[STG ? U : 1];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            if constexpr (STG) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    SX[u] = span_load<D>(x + gw * D, lane);
+                    if constexpr (!SQ) SY[u] = span_load<D>(y + gw * D, lane);
+                    return;
+                }
+            }
             if (g < nunits) {
-                load_stream(x + g * F::UNIT_DW, PX[u]);
-                if constexpr (!SQ) load_stream(y + g * F::UNIT_DW, PY[u]);
+                load_stream(x + g * D, PX[u]);
+                if constexpr (!SQ) load_stream(y + g * D, PY[u]);
             }
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            if constexpr (STG) {
+                if (g - lane + 63 < nunits) {
+                    span_unit<D>(slices[wave][0], lane, SX[u], PX[u]);
+                    if constexpr (!SQ) span_unit<D>(slices[wave][1], lane, SY[u], PY[u]);
+                }
+            }
             if (g < nunits) {
                 T bx[F::UNIT], by[F::UNIT];
                 unpack_elems<F, F::UNIT>(PX[u], bx);
