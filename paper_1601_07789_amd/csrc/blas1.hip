@@ -95,6 +95,25 @@ __device__ __forceinline__ void span_unit(uint32_t* slice, int lane, const SpanC
     __builtin_amdgcn_wave_barrier();
 }
 
+// The reverse: each lane's unit into the LDS slice, then the 64 D dwords
+// written as lane-contiguous 16-byte chunks (non-temporal).
+template <int D>
+__device__ __forceinline__ void span_store(uint32_t* __restrict__ base, uint32_t* slice, int lane, const uint32_t (&in)[D])
+{
+    constexpr int CH = 64 * D / 4;
+#pragma unroll
+    for (int j = 0; j < D; ++j) slice[D * lane + j] = in[j];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const u32x4 c0 = *reinterpret_cast<const u32x4*>(slice + 4 * lane);
+    u32x4 c1;
+    if (64 + lane < CH) c1 = *reinterpret_cast<const u32x4*>(slice + 4 * (64 + lane));
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_nontemporal_store(c0, reinterpret_cast<u32x4*>(base) + lane);
+    if (64 + lane < CH) __builtin_nontemporal_store(c1, reinterpret_cast<u32x4*>(base) + 64 + lane);
+}
+
 constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
@@ -104,6 +123,10 @@ __global__ void __launch_bounds__(kBlock)
 k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
 {
     using T = typename F::bits_t;
+    constexpr int D = F::UNIT_DW;
+    constexpr bool STG = D == 5 || D == 7;   // two-instruction packed units: written as wave spans
+    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][STG ? 64 * D : 4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
@@ -121,9 +144,15 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
                 words_to_bits<F, F::UNIT>(w[u], b);
 #pragma unroll
                 for (int e = 0; e < F::UNIT; ++e) b[e] = round_pack<F, MODE>(b[e]);
-                uint32_t P[F::UNIT_DW];
+                uint32_t P[D];
                 assemble_elems<F, F::UNIT>(b, P);
-                store_stream(dst + g * F::UNIT_DW, P);
+                if constexpr (STG) {
+                    if (g - lane + 63 < nunits) {   // wave-uniform: every lane in range and active
+                        span_store<D>(dst + (g - lane) * D, slices[wave], lane, P);
+                        return;
+                    }
+                }
+                store_stream(dst + g * D, P);
             }
         });
     }
@@ -151,19 +180,33 @@ k_unpack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t n
     // lane-contiguous KiB (non-temporal) instead.
     constexpr bool STAGE = OW == 8;
     __shared__ __attribute__((aligned(16))) uint32_t stage[STAGE ? kBlock / 64 : 1][STAGE ? 64 * OW : 4];
+    constexpr int D = NE * F::k / 4;          // input dwords per lane unit
+    constexpr bool STG = D == 5 || D == 7;   // two-instruction input units: read as wave spans
+    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][STG ? 64 * D : 4];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
-        uint32_t P[U][(NE * F::k / 4)];
+        uint32_t P[U][D];
+        SpanChunks<D> SP[STG ? U : 1];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_stream(src + g * (NE * F::k / 4), P[u]);
+            if constexpr (STG) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    SP[u] = span_load<D>(src + gw * D, lane);
+                    return;
+                }
+            }
+            if (g < nunits) load_stream(src + g * D, P[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            if constexpr (STG) {
+                if (g - lane + 63 < nunits) span_unit<D>(slices[wave], lane, SP[u], P[u]);
+            }
             uint32_t w[OW];
             if (g < nunits) {
                 T b[NE];
@@ -215,21 +258,42 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
        int64_t n)
 {
     using T = typename F::bits_t;
+    constexpr int D = F::UNIT_DW;
+    constexpr bool STG = D == 5 || D == 7;   // two-instruction units: read and written as wave spans
+    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][2][STG ? 64 * D : 4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
-        uint32_t PX[U][F::UNIT_DW], PY[U][F::UNIT_DW];
+        uint32_t PX[U][D], PY[U][D];
+        SpanChunks<D> SX[STG ? U : 1], SY[STG ? U : 1];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            if constexpr (STG) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    SX[u] = span_load<D>(x + gw * D, lane);
+                    SY[u] = span_load<D>(y + gw * D, lane);
+                    return;
+                }
+            }
             if (g < nunits) {
-                load_stream(x + g * F::UNIT_DW, PX[u]);
-                load_stream(y + g * F::UNIT_DW, PY[u]);
+                load_stream(x + g * D, PX[u]);
+                load_stream(y + g * D, PY[u]);
             }
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            bool span = false;
+            if constexpr (STG) {
+                span = g - lane + 63 < nunits;
+                if (span) {
+                    span_unit<D>(slices[wave][0], lane, SX[u], PX[u]);
+                    span_unit<D>(slices[wave][1], lane, SY[u], PY[u]);
+                }
+            }
             if (g < nunits) {
                 T bx[F::UNIT], by[F::UNIT];
                 unpack_elems<F, F::UNIT>(PX[u], bx);
@@ -237,9 +301,15 @@ k_axpy(typename F::native_t alpha, const uint32_t* __restrict__ x, uint32_t* __r
 #pragma unroll
                 for (int e = 0; e < F::UNIT; ++e)
                     by[e] = round_pack<F, MODE>(as_bits<F>(fma_n(alpha, as_native<F>(bx[e]), as_native<F>(by[e]))));
-                uint32_t P[F::UNIT_DW];
+                uint32_t P[D];
                 assemble_elems<F, F::UNIT>(by, P);
-                store_stream(y + g * F::UNIT_DW, P);
+                if constexpr (STG) {
+                    if (span) {
+                        span_store<D>(y + (g - lane) * D, slices[wave][0], lane, P);
+                        return;
+                    }
+                }
+                store_stream(y + g * D, P);
             }
         });
     }
@@ -261,26 +331,49 @@ __global__ void __launch_bounds__(kBlock)
 k_scale(typename F::native_t alpha, uint32_t* __restrict__ x, int64_t nunits, int64_t n)
 {
     using T = typename F::bits_t;
+    constexpr int D = F::UNIT_DW;
+    constexpr bool STG = D == 5 || D == 7;   // two-instruction units: read and written as wave spans
+    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][STG ? 64 * D : 4];
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t g0 = tid; g0 < nunits; g0 += nthreads * U) {
-        uint32_t PX[U][F::UNIT_DW];
+        uint32_t PX[U][D];
+        SpanChunks<D> SX[STG ? U : 1];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
-            if (g < nunits) load_stream(x + g * F::UNIT_DW, PX[u]);
+            if constexpr (STG) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    SX[u] = span_load<D>(x + gw * D, lane);
+                    return;
+                }
+            }
+            if (g < nunits) load_stream(x + g * D, PX[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * nthreads;
+            bool span = false;
+            if constexpr (STG) {
+                span = g - lane + 63 < nunits;
+                if (span) span_unit<D>(slices[wave], lane, SX[u], PX[u]);
+            }
             if (g < nunits) {
                 T bx[F::UNIT];
                 unpack_elems<F, F::UNIT>(PX[u], bx);
 #pragma unroll
                 for (int e = 0; e < F::UNIT; ++e) bx[e] = round_pack<F, MODE>(as_bits<F>(alpha * as_native<F>(bx[e])));
-                uint32_t P[F::UNIT_DW];
+                uint32_t P[D];
                 assemble_elems<F, F::UNIT>(bx, P);
-                store_stream(x + g * F::UNIT_DW, P);
+                if constexpr (STG) {
+                    if (span) {
+                        span_store<D>(x + (g - lane) * D, slices[wave], lane, P);
+                        return;
+                    }
+                }
+                store_stream(x + g * D, P);
             }
         });
     }
