@@ -15,6 +15,10 @@
 // LDS.  Both operand tiles are stored k-major (A transposed while unpacking)
 // with rows padded to 144 doubles, so the 16 lanes that share a k read 16
 // consecutive doubles and the two lane halves of a read hit disjoint banks.
+// A row of the transposed A is 288 dwords, 32 modulo the 64 banks, so the bank
+// of an A store depends on the m index alone: each wave therefore unpacks 32
+// consecutive rows of A x 2 adjacent units along k per instruction (not whole
+// rows), which puts exactly two lanes on every bank pair.
 // Epilogue: lane l holds rows l/16 + 4r (r = 0..3), column l%16, of each
 // 16 x 16 tile (the FP64 instruction's output order); the G lanes
 // of one dword-aligned group of columns pass their packed values to the
@@ -44,6 +48,18 @@ __device__ __forceinline__ void gemm_tile_coords_f64(int ntm, int ntn, int& tm, 
     const int gsize = (ntm - first_m) < GROUP ? (ntm - first_m) : GROUP;
     tm = first_m + (pid % per_group) % gsize;
     tn = (pid % per_group) / gsize;
+}
+
+// A unit u of the 128-row tile (A_UPR units per row) -> (row, unit along k):
+// chunk u / 64 picks a block of 32 rows and a pair of units, lane u % 64 the
+// row in the block and the unit in the pair.
+template <int A_UPR>
+__device__ __forceinline__ void a_unit_map(int u, int& row, int& uc)
+{
+    static_assert(A_UPR >= 2 && A_UPR % 2 == 0, "A units per row");
+    const int q = u / 64, l = u % 64;
+    row = (q % (GD_BM / 32)) * 32 + l % 32;
+    uc = (q / (GD_BM / 32)) * 2 + l / 32;
 }
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
@@ -80,7 +96,8 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
-            const int u = t + GD_THREADS * i, row = u / A_UPR, uc = u % A_UPR;
+            int row, uc;
+            a_unit_map<A_UPR>(t + GD_THREADS * i, row, uc);
             load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + uc * U) * KIN), ra[i]);
         }
 #pragma unroll
@@ -94,7 +111,8 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         double* Bs = lds[s][1];
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
-            const int u = t + GD_THREADS * i, row = u / A_UPR, uc = u % A_UPR;
+            int row, uc;
+            a_unit_map<A_UPR>(t + GD_THREADS * i, row, uc);
             uint64_t x[U];
             unpack_elems<FI, U>(ra[i], x);
 #pragma unroll
