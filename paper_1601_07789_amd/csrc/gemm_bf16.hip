@@ -234,6 +234,9 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
             // the next sub-step's A fragments are read halfway through the
             // current one, so the wave waits for at most one LDS read before an
             // MFMA group.  The group barriers keep the compiler to this order.
+            // The wave raises its issue priority for the block, so the other
+            // wave on the SIMD does its staging while this one feeds the
+            // matrix core.
             constexpr int KSN = BK / 32, JA = FN / 2;
             auto read_a = [&](int ks, int i) {
                 return *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
@@ -242,6 +245,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                 return *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
             };
             bf16x8_t a[2][FM], b[FN];
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int i = 0; i < FM; ++i) a[0][i] = read_a(0, i);
             b[0] = read_b(0, 0);
@@ -272,6 +276,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                     __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);   // MFMAs
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
         } else {
             const uint16_t* Al = a_tile(s, 1);
             const uint16_t* Bl = b_tile(s, 1);
