@@ -280,6 +280,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         } else {
             const uint16_t* Al = a_tile(s, 1);
             const uint16_t* Bl = b_tile(s, 1);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ks = 0; ks < BK / 32; ++ks) {
                 bf16x8_t a[FM], b[FN], al[FM], bl[FN];
@@ -306,6 +307,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bl[j], acc[i][j], 0, 0, 0);
                     }
             }
+            __builtin_amdgcn_s_setprio(0);
         }
     };
 
