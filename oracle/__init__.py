@@ -64,7 +64,6 @@ def _declare(lib: ctypes.CDLL) -> ctypes.CDLL:
         "fbo_axpy": (None, [c_int, c_int, c_sz, c_dbl, c_p, c_p]),
         "fbo_dot_naive": (c_dbl, [c_int, c_int, c_sz, c_p, c_p]),
         "fbo_dot_exact": (c_dbl, [c_int, c_int, c_sz, c_p, c_p]),
-        "fbo_dot_exact_f64": (c_dbl, [c_sz, c_p, ctypes.c_ssize_t, c_p, ctypes.c_ssize_t]),
         "fbo_gemv_naive": (None, [c_int, c_int, c_i64, c_i64, c_p, c_i64, c_p, c_p]),
         "fbo_gemv_exact": (None, [c_int, c_int, c_i64, c_i64, c_p, c_i64, c_p, c_p, c_p]),
         "fbo_gemm_entries": (None, [c_int, c_int, c_int, c_int, c_i64, c_p, c_i64, c_p, c_i64,
@@ -203,11 +202,6 @@ class Oracle:
         x = np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
         y = np.ascontiguousarray(y, dtype=np.uint8).reshape(-1)
         return float(self.lib.fbo_dot_exact(base, k, x.size // k, _ptr(x), _ptr(y)))
-
-    def dot_exact_f64(self, x: np.ndarray, y: np.ndarray) -> float:
-        x = np.ascontiguousarray(x, dtype=np.float64)
-        y = np.ascontiguousarray(y, dtype=np.float64)
-        return float(self.lib.fbo_dot_exact_f64(x.size, _ptr(x), 1, _ptr(y), 1))
 
     def gemv_naive(self, base: int, k: int, m: int, n: int, A: np.ndarray, lda: int,
                    x: np.ndarray) -> np.ndarray:

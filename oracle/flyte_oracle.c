@@ -47,6 +47,7 @@
  *   8 = the transposed GEMV multiplies column c by x in reversed row order
  *   9 = axpy computes alpha*y + x
  *  10 = the naive dot rounds each product before adding (no contraction)
+ *  11 = axpy ignores its rounding mode (always nearest even)
  */
 #include <math.h>
 #include <stdint.h>
@@ -259,7 +260,7 @@ static uint32_t bits_of_float(float v) { uint32_t u; memcpy(&u, &v, 4); return u
 /* is contracted (FP_CONTRACT on, Section 4.4 and Section 6).  alpha is */
 /* first rounded to the base type.                                      */
 /* ------------------------------------------------------------------ */
-void fbo_axpy(int base, int k, size_t n, double alpha, const uint8_t *x, uint8_t *y)
+void fbo_axpy_mode(int base, int k, int mode, size_t n, double alpha, const uint8_t *x, uint8_t *y)
 {
     for (size_t i = 0; i < n; ++i) {
         uint64_t r;
@@ -278,22 +279,18 @@ void fbo_axpy(int base, int k, size_t n, double alpha, const uint8_t *x, uint8_t
             double yi = elem_value(base, k, ya, i);
             r = bits_of_double(fma(alpha, xi, yi));
         }
+#if FBO_MUTATION == 11
         store_elem(y, k, i, fbo_pack_bits(base, k, r));
+#else
+        store_elem(y, k, i, fbo_pack_bits_mode(base, k, r, mode));
+#endif
     }
 }
 
-void fbo_axpy_mode(int base, int k, int mode, size_t n, double alpha, const uint8_t *x, uint8_t *y)
+/* axpy with the default cut, round to nearest even. */
+void fbo_axpy(int base, int k, size_t n, double alpha, const uint8_t *x, uint8_t *y)
 {
-    for (size_t i = 0; i < n; ++i) {
-        uint64_t r;
-        if (base == 32) {
-            float a = (float)alpha;
-            r = bits_of_float(fmaf(a, (float)elem_value(base, k, x, i), (float)elem_value(base, k, y, i)));
-        } else {
-            r = bits_of_double(fma(alpha, elem_value(base, k, x, i), elem_value(base, k, y, i)));
-        }
-        store_elem(y, k, i, fbo_pack_bits_mode(base, k, r, mode));
-    }
+    fbo_axpy_mode(base, k, FBO_RNE, n, alpha, x, y);
 }
 
 /* The paper's in-place BLAS-1 "scale" program: x[i] <- pack(alpha * x[i]),
@@ -494,16 +491,6 @@ double fbo_nrm2_exact(int base, int k, size_t n, const uint8_t *x)
     double s2 = fbo_dot_exact(base, k, n, x, x);
     if (base == 32) return (double)sqrtf((float)s2);
     return sqrt(s2);
-}
-
-/* Exact dot of two native double vectors with strides (for GEMM columns);
- * the result is rounded once to binary64. */
-double fbo_dot_exact_f64(size_t n, const double *x, ptrdiff_t incx, const double *y, ptrdiff_t incy)
-{
-    longacc a;
-    acc_init(&a);
-    for (size_t i = 0; i < n; ++i) acc_add_product(&a, x[(ptrdiff_t)i * incx], y[(ptrdiff_t)i * incy]);
-    return acc_round(&a, 53, -1022, 1023);
 }
 
 /* ------------------------------------------------------------------ */

@@ -1,8 +1,8 @@
 """Pins of the oracle's BLAS references (C3) against exact rational arithmetic.
 
-* axpy: fma(alpha, x, y) computed exactly with fractions, rounded once to the
-  base type, then rounded to the flyte format with the independent rational
-  rounding of ``valueround``; bit-exact.
+* axpy (every rounding mode): fma(alpha, x, y) computed exactly with
+  fractions, rounded once to the base type, then rounded to the flyte format
+  with the independent rational rounding of ``valueround``; bit-exact.
 * exact dot / gemv / gemm entries: the sum of products computed exactly with
   fractions and rounded once (binary64: Python's correctly rounded
   int/int division in ``float(Fraction)``; binary32: the rational rounder).
@@ -59,12 +59,18 @@ def frac_of_packed(orc, base, k, packed):
 
 # ---------------------------------------------------------------- axpy
 @pytest.mark.parametrize("base,k", FORMATS)
-def test_axpy_vs_rational(orc, base, k):
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_axpy_vs_rational(orc, base, k, mode):
+    """Every rounding mode: the exact fma in fractions, rounded once to the
+    base type, then cut to k bytes by the independent rational rounder in that
+    mode (nearest even, Section 5.2; toward zero, Section 5.1; to odd,
+    Section 7).  Mode 0 goes through fbo_axpy, the others through
+    fbo_axpy_mode."""
     n = 600
     x = orc.pack(base, k, wide_values(n, 11 + k, base))
     y = orc.pack(base, k, wide_values(n, 12 + k, base))
     alpha = float.fromhex("0x1.5555555555555p-2")   # RN(1/3) in binary64
-    got = orc.axpy(base, k, alpha, x, y)
+    got = orc.axpy(base, k, alpha, x, y, mode)
     a_native = np.float32(alpha) if base == 32 else alpha
     a = Fraction(float(a_native))
     xs, ys = frac_of_packed(orc, base, k, x), frac_of_packed(orc, base, k, y)
@@ -77,9 +83,14 @@ def test_axpy_vs_rational(orc, base, k):
         if r not in (vr.INF, vr.NINF) and r == 0:
             # sign of an exact zero sum under round-to-nearest: + unless both terms are -0
             neg = False
-        rk = r if r in (vr.INF, vr.NINF) else vr.round_rne(r, m + 1, emin, emax)
+        if r in (vr.INF, vr.NINF):
+            rk = r
+        elif mode == 0:
+            rk = vr.round_rne(r, m + 1, emin, emax)
+        else:
+            rk = vr.round_directed(r, m + 1, emin, mode)
         want = vr.encode(base, k, rk, neg)
-        assert int(gq[i]) == want, (i, base, k)
+        assert int(gq[i]) == want, (i, base, k, mode)
 
 
 def test_axpy_specials(orc):
@@ -276,8 +287,11 @@ BLAS_MUTATIONS = {
         [lambda o: test_dot_exact_vs_rational(o, 64, 5), lambda o: test_dot_exact_cancellation_and_tiny(o)]),
     8: ("transposed GEMV multiplies by the wrong x index",
         [lambda o: test_gemv_t_exact_vs_rational(o, 64, 3)]),
-    9: ("axpy computes alpha*y + x", [lambda o: test_axpy_vs_rational(o, 32, 3)]),
+    9: ("axpy computes alpha*y + x", [lambda o: test_axpy_vs_rational(o, 32, 3, 0),
+                                      lambda o: test_axpy_vs_rational(o, 64, 5, 2)]),
     10: ("naive dot rounds each product before adding", [lambda o: test_dot_naive_is_sequential_fma(o)]),
+    11: ("axpy ignores its rounding mode", [lambda o: test_axpy_vs_rational(o, 64, 5, 1),
+                                           lambda o: test_axpy_vs_rational(o, 32, 3, 2)]),
 }
 
 
