@@ -47,8 +47,11 @@
  *    except a per-(device, stream) workspace for partial sums (fb_dot,
  *    fb_dot_packed, fb_nrm2: 16 KiB; transposed fb_gemv_ex: slabs * n native
  *    values; {32,3} fb_gemm: the split operands, (M*K + K*N) * 4 bytes),
- *    allocated on first use on that stream and kept; growing it
- *    synchronises the stream.  Calls can be captured into a HIP graph; one
+ *    allocated on first use on that stream and kept.  A call that needs more
+ *    allocates a larger buffer and keeps the old one allocated as well (until
+ *    the process ends), so queued work and graphs captured earlier never
+ *    write freed memory; sizes at least double, so the retired buffers hold
+ *    less than the current one.  Calls can be captured into a HIP graph; one
  *    that needs a larger workspace than its stream has returns FB_ERR_RUNTIME
  *    during capture, so make one call of that size on the stream beforehand.
  *  - Input and output ranges must not overlap unless a call says so.
@@ -155,7 +158,8 @@ fb_status fb_gemv(fb_format f, int64_t m, int64_t n, const void *A, int64_t lda,
  * trans = 1: y (n elements) = A^T x, x has m values: each y_j is a fixed
  * sequence of fmas over slabs of rows plus a fixed-order sum of the slab
  * results (kept in the per-stream workspace, which grows to slabs * n native
- * values and then stays allocated; growing it synchronises the stream). */
+ * values and then stays allocated).  y is written even when m = 0 (zeros), so
+ * it must be valid whenever n > 0. */
 fb_status fb_gemv_ex(fb_format fa, fb_format fy, int32_t trans, int64_t m, int64_t n, const void *A,
                      int64_t lda, const void *x, void *y, hipStream_t stream);
 

@@ -74,8 +74,9 @@ auto dispatch_format(fb_format f, Fn&& fn)
 int device_cu_count();
 
 // Device scratch of at least `bytes` for calls on `stream` (one buffer per
-// device and stream, kept for the life of the process).  Growing it first
-// synchronises the stream, so no earlier call on it still uses the old buffer.
+// device and stream, kept for the life of the process).  Growing it
+// allocates a new buffer and keeps the old one allocated too, so work already
+// queued, and graphs captured earlier, still write valid memory.
 fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out);
 
 // One GEMV launch with a given tile (yk = 0: native y; else y packed in yk

@@ -70,10 +70,13 @@ __device__ __forceinline__ uint32_t bf16_rne(uint32_t u)
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
 
-// hi/lo split of a binary32 pattern (MODE 1).
+// hi/lo split of a binary32 pattern (MODE 1).  A NaN whose payload lies only
+// in the bits below hi would leave hi with a zero mantissa, an infinity, so
+// hi gets the quiet bit for every NaN: NaN stays NaN.
 __device__ __forceinline__ void split_hi_lo(uint32_t u, uint32_t& hi, uint32_t& lo)
 {
     hi = u >> 16;
+    if ((u & 0x7FFFFFFFu) > 0x7F800000u) hi |= 0x40u;
     const float r = __uint_as_float(u) - __uint_as_float(u & 0xFFFF0000u);
     lo = ((u & 0x7F800000u) == 0x7F800000u) ? 0u : bf16_rne(__float_as_uint(r));
 }

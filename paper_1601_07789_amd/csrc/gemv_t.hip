@@ -206,6 +206,10 @@ fb_status gemv_t_launch(fb_format fa, fb_format fy, int64_t m, int64_t n, const 
                         void* y, hipStream_t stream)
 {
     if (n == 0) return FB_OK;
+    // y (n elements) is written even when m = 0 (empty sums), and the shared
+    // argument checks stop at m = 0, so y is checked here
+    if (!y) return set_error(FB_ERR_ARG, "fb_gemv_ex: null y");
+    if (!aligned4(y)) return set_error(FB_ERR_ALIGN, "fb_gemv_ex: y must be 4-byte aligned");
     const int yk = (fy.k * 8 == fy.base) ? 0 : fy.k;
     return dispatch_format(fa, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;

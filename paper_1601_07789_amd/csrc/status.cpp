@@ -5,6 +5,7 @@
 #include <map>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 
@@ -43,13 +44,17 @@ fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out)
 {
     static std::mutex mu;
     static std::map<std::pair<int, hipStream_t>, std::pair<void*, size_t>> cache;
+    // Buffers handed out before a stream's workspace grew.  They are never
+    // freed: a graph captured from an earlier call still names its buffer, and
+    // replaying it must not write freed memory.  Each growth at least doubles
+    // the size, so these hold less than the current buffer.
+    static std::vector<void*> retired;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return set_error(FB_ERR_RUNTIME, "workspace: hipGetDevice failed");
     std::lock_guard<std::mutex> lk(mu);
     auto& slot = cache[std::make_pair(dev, stream)];
     if (slot.second < bytes) {
-        // allocating (or synchronising to release the old buffer) is not allowed
-        // while the stream is being captured into a graph
+        // allocating is not allowed while the stream is being captured into a graph
         hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
         if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone)
             return set_error(FB_ERR_RUNTIME,
@@ -58,13 +63,9 @@ fb_status stream_workspace(hipStream_t stream, size_t bytes, void** out)
                              bytes);
         size_t want = bytes < 2 * slot.second ? 2 * slot.second : bytes;
         if (want < 16384) want = 16384;
-        if (slot.first) {
-            if (hipStreamSynchronize(stream) != hipSuccess || hipFree(slot.first) != hipSuccess)
-                return set_error(FB_ERR_RUNTIME, "workspace: could not release the previous buffer");
-            slot = {nullptr, 0};
-        }
         void* p = nullptr;
         if (hipMalloc(&p, want) != hipSuccess) return set_error(FB_ERR_RUNTIME, "workspace: allocation failed");
+        if (slot.first) retired.push_back(slot.first);
         slot = {p, want};
     }
     *out = slot.first;

@@ -142,6 +142,42 @@ def _ptr(t: torch.Tensor | None) -> int | None:
     return None if t is None else t.data_ptr()
 
 
+def _arg(t, name: str, nbytes: int, dtype: torch.dtype | None = None, like: torch.Tensor | None = None) -> int:
+    """Checks a tensor handed to the library and returns its device address.
+
+    The kernels read and write raw device memory through the pointer, so a
+    host tensor, a strided view or a buffer smaller than the call touches
+    would be an out-of-bounds device access; each is refused here instead.
+    dtype None accepts any element type (packed bytes may be viewed as
+    anything); otherwise the tensor must have that dtype."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: tensor is on {t.device}, the library needs device memory")
+    if like is not None and t.device != like.device:
+        raise ValueError(f"{name}: tensor is on {t.device}, the call's other operands on {like.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    have = t.numel() * t.element_size()
+    if have < nbytes:
+        raise ValueError(f"{name}: the call touches {nbytes} bytes, the tensor holds {have}")
+    return t.data_ptr()
+
+
+def _out_dtype(base: int, k: int) -> torch.dtype:
+    """Element type of an output in format (base, k): native when k is the base width, else bytes."""
+    return native_dtype(base) if 8 * k == base else torch.uint8
+
+
+def _mat_bytes(rows: int, cols: int, ld: int, elem: int) -> int:
+    """Bytes spanned by a rows x cols row-major matrix with leading dimension ld."""
+    if rows <= 0 or cols <= 0:
+        return 0
+    return ((rows - 1) * ld + cols) * elem
+
+
 # ---------------------------------------------------------------- codec
 def pack(f, src: torch.Tensor, out: torch.Tensor | None = None, n: int | None = None, stream=None):
     """Rounds native values (float32 for base 32, float64 for base 64) to k-byte elements
@@ -150,7 +186,9 @@ def pack(f, src: torch.Tensor, out: torch.Tensor | None = None, n: int | None = 
     n = src.numel() if n is None else n
     if out is None:
         out = torch.empty(n * k, dtype=torch.uint8, device=src.device)
-    _check(load().fb_pack(fmt(f), _ptr(src), _ptr(out), n, _stream(stream)))
+    ps = _arg(src, "pack: src", n * base // 8, native_dtype(base))
+    po = _arg(out, "pack: out", n * k, None, src)
+    _check(load().fb_pack(fmt(f), ps, po, n, _stream(stream)))
     return out
 
 
@@ -159,7 +197,9 @@ def unpack(f, packed: torch.Tensor, n: int | None = None, out: torch.Tensor | No
     n = packed.numel() // k if n is None else n
     if out is None:
         out = torch.empty(n, dtype=native_dtype(base), device=packed.device)
-    _check(load().fb_unpack(fmt(f), _ptr(packed), _ptr(out), n, _stream(stream)))
+    pp = _arg(packed, "unpack: packed", n * k)
+    po = _arg(out, "unpack: out", n * base // 8, native_dtype(base), packed)
+    _check(load().fb_unpack(fmt(f), pp, po, n, _stream(stream)))
     return out
 
 
@@ -169,7 +209,10 @@ def dot(f, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Te
     n = x.numel() // k if n is None else n
     if out is None:
         out = torch.empty((), dtype=native_dtype(base), device=x.device)
-    _check(load().fb_dot(fmt(f), n, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
+    px = _arg(x, "dot: x", n * k)
+    py = _arg(y, "dot: y", n * k, None, x)
+    po = _arg(out, "dot: out", base // 8, native_dtype(base), x)
+    _check(load().fb_dot(fmt(f), n, px, py, po, _stream(stream)))
     return out
 
 
@@ -177,7 +220,9 @@ def axpy(f, alpha: float, x: torch.Tensor, y: torch.Tensor, n: int | None = None
     """y <- pack(alpha * x + y), in place on the packed tensor y."""
     base, k = f[0], f[1]
     n = y.numel() // k if n is None else n
-    _check(load().fb_axpy(fmt(f), n, float(alpha), _ptr(x), _ptr(y), _stream(stream)))
+    py = _arg(y, "axpy: y", n * k)
+    px = _arg(x, "axpy: x", n * k, None, y)
+    _check(load().fb_axpy(fmt(f), n, float(alpha), px, py, _stream(stream)))
     return y
 
 
@@ -185,7 +230,8 @@ def scale(f, alpha: float, x: torch.Tensor, n: int | None = None, stream=None):
     """x <- pack(alpha * x), in place on the packed tensor x."""
     base, k = f[0], f[1]
     n = x.numel() // k if n is None else n
-    _check(load().fb_scale(fmt(f), n, float(alpha), _ptr(x), _stream(stream)))
+    px = _arg(x, "scale: x", n * k)
+    _check(load().fb_scale(fmt(f), n, float(alpha), px, _stream(stream)))
     return x
 
 
@@ -195,21 +241,35 @@ def nrm2(f, x: torch.Tensor, n: int | None = None, out: torch.Tensor | None = No
     n = x.numel() // k if n is None else n
     if out is None:
         out = torch.empty((), dtype=native_dtype(base), device=x.device)
-    _check(load().fb_nrm2(fmt(f), n, _ptr(x), _ptr(out), _stream(stream)))
+    px = _arg(x, "nrm2: x", n * k)
+    po = _arg(out, "nrm2: out", base // 8, native_dtype(base), x)
+    _check(load().fb_nrm2(fmt(f), n, px, po, _stream(stream)))
     return out
 
 
 # ---------------------------------------------------------------- BLAS 2
+def _gemv_args(what, base, k, m, n, lda, A, x, y, ydtype, ybytes, trans=False):
+    """Checks A (m x n, leading dimension lda), x and y of a GEMV; returns their addresses."""
+    nx, ny = (m, n) if trans else (n, m)
+    if m > 0 and lda < n:
+        raise ValueError(f"{what}: lda {lda} < n {n}")
+    pa = _arg(A, f"{what}: A", _mat_bytes(m, n, lda, k))
+    px = _arg(x, f"{what}: x", nx * base // 8, native_dtype(base), A)
+    py = _arg(y, f"{what}: y", ny * ybytes, ydtype, A)
+    return pa, px, py
+
+
 def gemv(f, A: torch.Tensor, m: int, n: int, x: torch.Tensor, y: torch.Tensor | None = None,
          lda: int | None = None, config: int | None = None, stream=None):
     base, k = f[0], f[1]
     lda = n if lda is None else lda
     if y is None:
         y = torch.empty(m, dtype=native_dtype(base), device=A.device)
+    pa, px, py = _gemv_args("gemv", base, k, m, n, lda, A, x, y, native_dtype(base), base // 8)
     if config is None:
-        _check(load().fb_gemv(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), _stream(stream)))
+        _check(load().fb_gemv(fmt(f), m, n, pa, lda, px, py, _stream(stream)))
     else:
-        _check(load().fb_gemv_config(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), config, _stream(stream)))
+        _check(load().fb_gemv_config(fmt(f), m, n, pa, lda, px, py, config, _stream(stream)))
     return y
 
 
@@ -224,8 +284,8 @@ def gemv_ex(fa, fy, trans: bool, A: torch.Tensor, m: int, n: int, x: torch.Tenso
             y = torch.empty(ny, dtype=native_dtype(base), device=A.device)
         else:
             y = torch.empty(ny * fy[1], dtype=torch.uint8, device=A.device)
-    _check(load().fb_gemv_ex(fmt(fa), fmt(fy), 1 if trans else 0, m, n, _ptr(A), lda, _ptr(x), _ptr(y),
-                             _stream(stream)))
+    pa, px, py = _gemv_args("gemv_ex", base, fa[1], m, n, lda, A, x, y, _out_dtype(base, fy[1]), fy[1], trans)
+    _check(load().fb_gemv_ex(fmt(fa), fmt(fy), 1 if trans else 0, m, n, pa, lda, px, py, _stream(stream)))
     return y
 
 
@@ -235,7 +295,10 @@ def dot_packed(f, fr, x: torch.Tensor, y: torch.Tensor, n: int | None = None, ou
     n = x.numel() // f[1] if n is None else n
     if out is None:
         out = torch.empty(fr[1], dtype=torch.uint8, device=x.device)
-    _check(load().fb_dot_packed(fmt(f), fmt(fr), n, _ptr(x), _ptr(y), _ptr(out), _stream(stream)))
+    px = _arg(x, "dot_packed: x", n * f[1])
+    py = _arg(y, "dot_packed: y", n * f[1], None, x)
+    po = _arg(out, "dot_packed: out", fr[1], None, x)
+    _check(load().fb_dot_packed(fmt(f), fmt(fr), n, px, py, po, _stream(stream)))
     return out
 
 
@@ -253,8 +316,8 @@ def gemv_config_info(config: int):
 def tune_gemv(f, A, m, n, x, y, lda=None, reps: int = 10, stream=None) -> int:
     lda = n if lda is None else lda
     best = _I32(-1)
-    _check(load().fb_tune_gemv(fmt(f), m, n, _ptr(A), lda, _ptr(x), _ptr(y), reps, ctypes.byref(best),
-                               _stream(stream)))
+    pa, px, py = _gemv_args("tune_gemv", f[0], f[1], m, n, lda, A, x, y, native_dtype(f[0]), f[0] // 8)
+    _check(load().fb_tune_gemv(fmt(f), m, n, pa, lda, px, py, reps, ctypes.byref(best), _stream(stream)))
     return best.value
 
 
@@ -297,7 +360,10 @@ class BatchedGemv:
         self.items = items               # keeps the tensors alive
         arr = (fb_gemv_desc * max(1, len(items)))()
         for i, it in enumerate(items):
-            arr[i] = fb_gemv_desc(fmt(it.f), it.m, it.n, 0, it.lda, _ptr(it.A), _ptr(it.x), _ptr(it.y))
+            base, k = it.f[0], it.f[1]
+            pa, px, py = _gemv_args(f"batched item {i}", base, k, it.m, it.n, it.lda, it.A, it.x, it.y,
+                                    native_dtype(base), base // 8)
+            arr[i] = fb_gemv_desc(fmt(it.f), it.m, it.n, 0, it.lda, pa, px, py)
         plan = _P()
         _check(load().fb_gemv_batched_plan(arr, len(items), ctypes.byref(plan)))
         self._plan = plan
@@ -347,6 +413,11 @@ def gemm(fa, fb, fc, M: int, N: int, K: int, A: torch.Tensor, B: torch.Tensor, C
             C = torch.empty(M * ldc, dtype=native_dtype(fc[0]), device=A.device)
         else:
             C = torch.empty(M * ldc * fc[1], dtype=torch.uint8, device=A.device)
-    _check(load().fb_gemm_ex(fmt(fa), fmt(fb), fmt(fc), M, N, K, _ptr(A), lda, _ptr(B), ldb, _ptr(C), ldc,
-                             flags, _stream(stream)))
+    if (M > 0 and K > 0 and lda < K) or (K > 0 and N > 0 and ldb < N) or (M > 0 and N > 0 and ldc < N):
+        raise ValueError(f"gemm: leading dimensions ({lda}, {ldb}, {ldc}) below the row lengths ({K}, {N}, {N})")
+    pa = _arg(A, "gemm: A", _mat_bytes(M, K, lda, fa[1]))
+    pb = _arg(B, "gemm: B", _mat_bytes(K, N, ldb, fb[1]), None, A)
+    pc = _arg(C, "gemm: C", _mat_bytes(M, N, ldc, fc[1]), _out_dtype(fc[0], fc[1]), A)
+    _check(load().fb_gemm_ex(fmt(fa), fmt(fb), fmt(fc), M, N, K, pa, lda, pb, ldb, pc, ldc, flags,
+                             _stream(stream)))
     return C

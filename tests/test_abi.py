@@ -92,6 +92,9 @@ def test_gemv_argument_errors(lib):
     assert lib.fb_gemv_ex(F(64, 5), F(64, 3), 2, 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_ARG
     assert lib.fb_gemv_ex(F(64, 5), F(64, 3, 3), 0, 4, 4, FAKE, 4, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
     assert lib.fb_dot_packed(F(64, 5), F(32, 2), 4, FAKE, FAKE, FAKE, None) == flyte.FB_ERR_FORMAT
+    # the transposed GEMV writes its n outputs even when m = 0, so y is checked then too
+    assert lib.fb_gemv_ex(F(64, 8), F(64, 8), 1, 0, 4, None, 4, None, None, None) == flyte.FB_ERR_ARG
+    assert lib.fb_gemv_ex(F(64, 8), F(64, 8), 1, 0, 4, None, 4, None, MISALIGNED, None) == flyte.FB_ERR_ALIGN
 
 
 def test_gemm_argument_errors(lib):
