@@ -254,7 +254,8 @@ def _gemv_args(what, base, k, m, n, lda, A, x, y, ydtype, ybytes, trans=False):
     if m > 0 and lda < n:
         raise ValueError(f"{what}: lda {lda} < n {n}")
     pa = _arg(A, f"{what}: A", _mat_bytes(m, n, lda, k))
-    px = _arg(x, f"{what}: x", nx * base // 8, native_dtype(base), A)
+    # with no outputs nothing is read
+    px = _arg(x, f"{what}: x", nx * base // 8 if ny > 0 else 0, native_dtype(base), A)
     py = _arg(y, f"{what}: y", ny * ybytes, ydtype, A)
     return pa, px, py
 

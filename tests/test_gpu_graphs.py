@@ -71,3 +71,39 @@ def test_capture_and_replay(dev, orc):
         for a, b in zip([y, yt, d, v], ref):
             assert np.array_equal(a.cpu().numpy().reshape(-1).view(np.uint8),
                                   b.cpu().numpy().reshape(-1).view(np.uint8)), rep
+
+
+def test_replay_after_workspace_growth(dev, orc):
+    """A graph captured with the stream's small workspace (dot partials) keeps
+    working after a later eager call on the same stream grows that workspace
+    (a {32,3} GEMM's split planes): the old buffer stays allocated, so each
+    replay writes valid memory and returns the captured call's bits."""
+    import torch
+    log("graph replay after workspace growth")
+    t = lambda a: torch.from_numpy(a).to(dev)
+    nv = 200003
+    u = t(orc.pack(64, 5, workloads.uniform(nv, 710)))
+    v = t(orc.pack(64, 5, workloads.uniform(nv, 711)))
+    d = torch.empty((), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)      # a fresh stream: its workspace starts small
+    with torch.cuda.stream(s):
+        flyte.dot((64, 5), u, v, out=d, stream=s)
+    torch.cuda.synchronize()
+    ref = d.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        flyte.dot((64, 5), u, v, out=d, stream=s)
+    torch.cuda.synchronize()
+    M = N = K = 512
+    A = t(orc.pack(32, 3, workloads.normal(M * K, 712)))
+    B = t(orc.pack(32, 3, workloads.normal(K * N, 713)))
+    with torch.cuda.stream(s):
+        C = flyte.gemm((32, 3), (32, 3), (32, 4), M, N, K, A, B, stream=s)   # grows the workspace
+    torch.cuda.synchronize()
+    for rep in range(3):
+        d.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy().reshape(-1).view(np.uint8), ref.cpu().numpy().reshape(-1).view(np.uint8)), rep
+    assert torch.isfinite(C).all().item()
