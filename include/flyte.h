@@ -116,6 +116,19 @@ fb_status fb_unpack(fb_format f, const void *src_packed, void *dst_native, size_
 fb_status fb_dot(fb_format f, size_t n, const void *x, const void *y, void *result,
                  hipStream_t stream);
 
+/* fb_dot for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): same arguments,
+ * kernels, order and result bits as fb_dot, but the partial sums go to a
+ * static device array of 1984 binary64 values (15.5 KiB) instead of the
+ * stream workspace, so the call allocates nothing, ever.  Every n is
+ * accepted (the partial count is capped at 1984 whatever n is).  The array
+ * exists once per device and is shared by all calls on that device: calls
+ * that overlap in time on one device (on different streams, or from
+ * different threads) race on it and give wrong results; calls ordered on one
+ * stream are fine.  Nothing in it needs to start at zero. */
+fb_status fb_dot_noalloc(fb_format f, size_t n, const void *x, const void *y, void *result,
+                         hipStream_t stream);
+
 /* fb_dot with the result stored in format fr (same base as f): the base-type
  * sum rounded once in fr's rounding mode, fr.k bytes in device memory. */
 fb_status fb_dot_packed(fb_format f, fb_format fr, size_t n, const void *x, const void *y,

@@ -10,6 +10,9 @@
 // workgroups per CU and kept off powers of two (stream_grid).  The fewer than a unit of elements after the last whole
 // unit are handled one by one with byte accesses by the first threads of
 // block 0.
+#include <mutex>
+#include <unordered_map>
+
 #include "codec.hpp"
 #include "common.hpp"
 
@@ -601,31 +604,97 @@ extern "C" fb_status fb_axpy(fb_format f, size_t n, double alpha, const void* x,
     });
 }
 
-extern "C" fb_status fb_dot(fb_format f, size_t n, const void* x, const void* y, void* result, hipStream_t stream)
+// The two launches of a dot product with its partial sums in `partials`
+// (room for kMaxDotBlocks native values).  Arguments are validated.
+static fb_status dot_launch(fb_format f, size_t n, const void* x, const void* y, void* result, void* partials,
+                            hipStream_t stream)
 {
-    if (!result) return set_error(FB_ERR_ARG, "fb_dot: null result");
-    if (!aligned4(result)) return set_error(FB_ERR_ALIGN, "fb_dot: result must be 4-byte aligned");
-    fb_status st = check_vec("fb_dot", f, x, y, n);
-    if (st != FB_OK) return st;
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         using N = typename F::native_t;
-        if (n == 0) {
-            k_store_zero<N><<<1, 1, 0, stream>>>(static_cast<N*>(result));
-            return check_launch("fb_dot");
-        }
-        void* ws = nullptr;
-        fb_status s2 = dot_workspace(stream, &ws);
-        if (s2 != FB_OK) return s2;
         const int64_t nunits = (int64_t)(n / F::UNIT);
         int grid = stream_grid(nunits, kUnroll);
         if (grid > kMaxDotBlocks) grid = kMaxDotBlocks;
         k_dot_partial<F, kUnroll><<<grid, kBlock, 0, stream>>>(static_cast<const uint32_t*>(x),
                                                                static_cast<const uint32_t*>(y), nunits,
-                                                               (int64_t)n, static_cast<N*>(ws));
-        k_dot_final<N, false><<<1, kBlock, 0, stream>>>(static_cast<const N*>(ws), grid, static_cast<N*>(result));
+                                                               (int64_t)n, static_cast<N*>(partials));
+        k_dot_final<N, false><<<1, kBlock, 0, stream>>>(static_cast<const N*>(partials), grid, static_cast<N*>(result));
         return check_launch("fb_dot");
     });
+}
+
+static fb_status dot_zero(fb_format f, void* result, hipStream_t stream)
+{
+    return dispatch_format(f, [&](auto tag) {
+        using N = typename Fmt<decltype(tag.first)::value, decltype(tag.second)::value>::native_t;
+        k_store_zero<N><<<1, 1, 0, stream>>>(static_cast<N*>(result));
+        return check_launch("fb_dot");
+    });
+}
+
+static fb_status dot_check(const char* what, fb_format f, size_t n, const void* x, const void* y, void* result)
+{
+    if (!result) return set_error(FB_ERR_ARG, "%s: null result", what);
+    if (!aligned4(result)) return set_error(FB_ERR_ALIGN, "%s: result must be 4-byte aligned", what);
+    return check_vec(what, f, x, y, n);
+}
+
+extern "C" fb_status fb_dot(fb_format f, size_t n, const void* x, const void* y, void* result, hipStream_t stream)
+{
+    fb_status st = dot_check("fb_dot", f, n, x, y, result);
+    if (st != FB_OK) return st;
+    if (n == 0) return dot_zero(f, result, stream);
+    void* ws = nullptr;
+    st = dot_workspace(stream, &ws);
+    if (st != FB_OK) return st;
+    return dot_launch(f, n, x, y, result, ws, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free dot
+// The partial sums of fb_dot_noalloc live in this array instead of the stream
+// workspace: kMaxDotBlocks binary64 values (15.5 KiB), one copy per device,
+// kept until the process ends and shared by every call on that device.  Host
+// code never names it directly (on the host the name is only a stand-in): its
+// device address is looked up once per device and kept.
+constexpr size_t kScratchBytes = (size_t)kMaxDotBlocks * sizeof(double);
+static __device__ __align__(256) double scratch[kMaxDotBlocks];
+
+static fb_status scratch_address(void** out)
+{
+    static std::mutex mu;
+    static std::unordered_map<int, void*> addr;   // device -> that device's copy of scratch
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return set_error(FB_ERR_RUNTIME, "fb_dot_noalloc: hipGetDevice failed");
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(FB_ERR_RUNTIME, "fb_dot_noalloc: hipGetSymbolAddress failed on device %d: %s", dev,
+                             hipGetErrorString(e));
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return FB_OK;
+}
+
+extern "C" fb_status fb_dot_noalloc(fb_format f, size_t n, const void* x, const void* y, void* result,
+                                    hipStream_t stream)
+{
+    fb_status st = dot_check("fb_dot_noalloc", f, n, x, y, result);
+    if (st != FB_OK) return st;
+    if (n == 0) return dot_zero(f, result, stream);
+    // The partial count is capped at kMaxDotBlocks whatever n is, so every n
+    // fits; the check guards the size of the array against a larger cap.
+    const size_t need = (size_t)kMaxDotBlocks * (f.base / 8);
+    if (need > kScratchBytes)
+        return set_error(FB_ERR_UNSUPPORTED, "fb_dot_noalloc: %zu bytes of partial sums exceed the %zu-byte scratch",
+                         need, kScratchBytes);
+    void* p = nullptr;
+    st = scratch_address(&p);
+    if (st != FB_OK) return st;
+    return dot_launch(f, n, x, y, result, p, stream);
 }
 
 extern "C" fb_status fb_dot_packed(fb_format f, fb_format fr, size_t n, const void* x, const void* y, void* result,

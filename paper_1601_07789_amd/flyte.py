@@ -51,6 +51,7 @@ _SIGS = {
     "fb_pack": (_I32, [fb_format, _P, _P, _SZ, _P]),
     "fb_unpack": (_I32, [fb_format, _P, _P, _SZ, _P]),
     "fb_dot": (_I32, [fb_format, _SZ, _P, _P, _P, _P]),
+    "fb_dot_noalloc": (_I32, [fb_format, _SZ, _P, _P, _P, _P]),
     "fb_axpy": (_I32, [fb_format, _SZ, _DBL, _P, _P, _P]),
     "fb_scale": (_I32, [fb_format, _SZ, _DBL, _P, _P]),
     "fb_nrm2": (_I32, [fb_format, _SZ, _P, _P, _P]),
@@ -213,6 +214,18 @@ def dot(f, x: torch.Tensor, y: torch.Tensor, n: int | None = None, out: torch.Te
     py = _arg(y, "dot: y", n * k, None, x)
     po = _arg(out, "dot: out", base // 8, native_dtype(base), x)
     _check(load().fb_dot(fmt(f), n, px, py, po, _stream(stream)))
+    return out
+
+
+def dot_noalloc(f, x: torch.Tensor, y: torch.Tensor, out: torch.Tensor, n: int | None = None, stream=None):
+    """dot through the allocation-free entry point (partial sums in a static device
+    array shared by every call on the device; out must be given)."""
+    base, k = f[0], f[1]
+    n = x.numel() // k if n is None else n
+    px = _arg(x, "dot_noalloc: x", n * k)
+    py = _arg(y, "dot_noalloc: y", n * k, None, x)
+    po = _arg(out, "dot_noalloc: out", base // 8, native_dtype(base), x)
+    _check(load().fb_dot_noalloc(fmt(f), n, px, py, po, _stream(stream)))
     return out
 
 
