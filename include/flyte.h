@@ -46,7 +46,8 @@
  *  - Nothing aborts, throws or prints.  Hot calls allocate no device memory,
  *    except a per-(device, stream) workspace for partial sums (fb_dot,
  *    fb_dot_packed, fb_nrm2: 16 KiB; transposed fb_gemv_ex: slabs * n native
- *    values; {32,3} fb_gemm: the split operands, (M*K + K*N) * 4 bytes),
+ *    values; fb_gemm on {64,2..4}: scales and band flags, about 73 bytes per
+ *    row of A and column of B),
  *    allocated on first use on that stream and kept.  A call that needs more
  *    allocates a larger buffer and keeps the old one allocated as well (until
  *    the process ends), so queued work and graphs captured earlier never
@@ -272,35 +273,55 @@ void fb_plan_destroy(fb_plan *plan);
 
 /* C = A B with A M x K (lda), B K x N (ldb), C M x N (ldc), row-major: the
  * matrix-matrix benchmark of Section 6 with the codec fused into the operand
- * loaders and, for a packed C, into the epilogue (Sections 3.2, 5.2).
- * Supported combinations (others: FB_ERR_UNSUPPORTED):
+ * loaders and, for a packed C, into the epilogue (Sections 3.2, 4.3, 5.2).
+ * Any M, N, K >= 0 (edge tiles and the K tail are bounded; no byte past a
+ * row's last element is read and no C element outside the M x N block is
+ * written).  Supported combinations (others: FB_ERR_UNSUPPORTED):
  *  - fa = fb = {32,2}, fc = {32,4}: the stored 2-byte patterns are bfloat16
  *    operands of BF16 matrix-core instructions, FP32 accumulation, FP32 C.
- *  - fa = fb = {32,3}, fc = {32,4}: each operand element is split into hi =
- *    its top two bytes (a bfloat16) and lo = x - hi rounded to bfloat16 (exact
- *    for normal x with biased exponent >= 9; 0 for Inf/NaN); C = hi*hi +
- *    hi*lo + lo*hi in FP32 accumulators (lo*lo dropped): three BF16 products.
- *    The split is written once to the stream workspace ((M*K + K*N) * 4
- *    bytes) by a pass before the products.  An infinite element (hi = Inf,
- *    lo = 0) can meet a partner whose lo is 0 in a hi*lo term, Inf * 0, so
- *    entries whose exact value is +-Inf may come out NaN; NaN stays NaN.
- *  - fa = fb = any binary64 format {64,2..8}, fc any binary64 format: operands
- *    unpacked to FP64, FP64 matrix-core products and accumulation (products
- *    exact for k <= 4), C rounded to fc in the epilogue in fc's rounding mode
- *    (one rounding of the FP64 result).
- * Sizes: M, N multiples of 128; K a multiple of 64 (binary32) or 16
- * (binary64); other shapes FB_ERR_UNSUPPORTED.  K = 0 gives C = +0.  Rows of
- * A, B and C start 4-byte aligned (ld * k a multiple of 4), else FB_ERR_ALIGN. */
+ *  - fa = fb = {32,3}, fc = {32,4}: each operand element is split, while it is
+ *    loaded, into hi = its top two bytes (a bfloat16; a NaN gets the quiet
+ *    bit, so it stays NaN) and lo = x - hi rounded to bfloat16 (exact for
+ *    biased exponent >= 9; 0 for Inf/NaN); C = hi*hi + hi*lo + lo*hi in FP32
+ *    accumulators (lo*lo dropped, |lo| < 2^-7 |x|): three BF16 products.  An
+ *    infinite element (hi = Inf, lo = 0) can meet a partner whose lo is 0 in a
+ *    hi*lo term, Inf * 0, so entries whose exact value is +-Inf may come out
+ *    NaN; NaN stays NaN.  No workspace.
+ *  - fa = fb = {64,2}, {64,3} or {64,4} (5, 13, 21 significant bits), fc any
+ *    binary64 format: every row of A and column of B is scaled by an exact
+ *    power of two (its largest element to [1, 2)), each scaled element cut
+ *    into 1, 2 or 3 bfloat16 pieces (8 + 8 + 5 bits, exact), the products of
+ *    pieces (exact in FP32) summed on BF16 matrix cores in FP32, scaled back
+ *    exactly in FP64 and rounded to fc in the epilogue.  By default the
+ *    products of pieces i, j with i + j <= k - 2 are formed ({64,3}: 3 of 4,
+ *    dropping at most 2^-14 |a||b| per term; {64,4}: 6 of 9, dropping below
+ *    2^-20 |a||b|).  A row or column with an element more than 2^40 below its
+ *    largest, a binary64 subnormal, Inf or NaN cannot be scaled exactly: every
+ *    128 x 128 tile of C in its 128-row band of A (128-column band of B) is
+ *    then computed as below, on FP64 matrix cores.  A pass before the GEMM
+ *    finds the scales and bands; they live in the per-stream workspace
+ *    (about 73 bytes per row of A plus column of B).
+ *  - fa = fb = any binary64 format {64,2..8} (k >= 5, or with FB_GEMM_FP64),
+ *    fc any binary64 format: operands unpacked to FP64, FP64 matrix-core
+ *    products and accumulation (products exact for k <= 4), C rounded to fc
+ *    in the epilogue in fc's rounding mode (one rounding of the FP64 result).
+ * K = 0 gives C = +0.  Rows of A, B and C start 4-byte aligned (ld * k a
+ * multiple of 4), else FB_ERR_ALIGN. */
 fb_status fb_gemm(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,
                   const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
                   hipStream_t stream);
 
-/* fb_gemm with options.  FB_GEMM_FOUR_PRODUCTS ({32,3} operands only): adds
- * lo*lo to the three products, so every product of the split operands is
- * exact and only the FP32 accumulation rounds.  Other flag bits: FB_ERR_ARG. */
+/* fb_gemm with options.  FB_GEMM_ALL_PRODUCTS (split operands: {32,3}, and
+ * {64,3}, {64,4} on the bfloat16 pieces): every product of pieces is formed
+ * (4 for {32,3} and {64,3}, 9 for {64,4}), so only the FP32 accumulation
+ * rounds.  FB_GEMM_FP64 (binary64 operands): the FP64 matrix-core path for
+ * k <= 4 as well.  Other flag bits: FB_ERR_ARG; a flag that does not apply
+ * to the formats: FB_ERR_UNSUPPORTED. */
 typedef enum fb_gemm_flags {
     FB_GEMM_DEFAULT = 0,
-    FB_GEMM_FOUR_PRODUCTS = 1
+    FB_GEMM_ALL_PRODUCTS = 1,
+    FB_GEMM_FOUR_PRODUCTS = 1,   /* the {32,3} name of FB_GEMM_ALL_PRODUCTS */
+    FB_GEMM_FP64 = 2
 } fb_gemm_flags;
 
 fb_status fb_gemm_ex(fb_format fa, fb_format fb, fb_format fc, int64_t M, int64_t N, int64_t K,

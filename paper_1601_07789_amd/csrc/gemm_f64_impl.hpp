@@ -69,10 +69,37 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Loads the N dwords of one unit whose first nbytes bytes are valid (0 <=
+// nbytes <= 4 N): dwords wholly inside are loaded, a straddling dword is
+// assembled from byte loads, the rest are zero.  Nothing past the valid bytes
+// is read.
+template <int N>
+__device__ __forceinline__ void gd_load_edge(const uint8_t* p, int nbytes, uint32_t (&out)[N])
+{
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+        if (4 * w + 4 <= nbytes) {
+            out[w] = *reinterpret_cast<const uint32_t*>(p + 4 * w);
+        } else {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (4 * w + b < nbytes) v |= (uint32_t)p[4 * w + b] << (8 * b);
+            out[w] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ int gd_clamp(int v, int hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
+
+// bandA, bandB (may be null): when given, only the tiles whose 128-row band of
+// A or 128-column band of B is flagged are computed (the rest belong to the
+// bfloat16-piece GEMM of the same call).
 template <int KIN, int KOUT, int MODE>
 __global__ void __launch_bounds__(GD_THREADS, 2)
 k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
-           uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K)
+           uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K, const uint8_t* __restrict__ bandA,
+           const uint8_t* __restrict__ bandB)
 {
     using FI = Fmt<64, KIN>;
     using FO = Fmt<64, KOUT>;
@@ -82,28 +109,37 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     static_assert(A_UNITS >= 1 && B_UNITS >= 1, "tile too small for the unit");
     __shared__ __attribute__((aligned(16))) double lds[2][2][GD_BK * GD_ROW];   // [stage][A^T, B][k][m or n]
 
-    const int ntm = M / GD_BM, ntn = N / GD_BN;
+    const int ntm = (M + GD_BM - 1) / GD_BM, ntn = (N + GD_BN - 1) / GD_BN;
     int tm, tn;
     gemm_tile_coords_f64(ntm, ntn, tm, tn);
+    if (bandA && !bandA[tm] && !bandB[tn]) return;
     const int m0 = tm * GD_BM, n0 = tn * GD_BN;
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
     const int wm = wid / 2, wn = wid % 2;
+    const bool interior = m0 + GD_BM <= M && n0 + GD_BN <= N;
 
     uint32_t ra[A_UNITS][FI::UNIT_DW], rb[B_UNITS][FI::UNIT_DW];
     constexpr int A_UPR = GD_BK / U;    // A units per row of the tile
     constexpr int B_UPR = GD_BN / U;    // B units per row of the tile
 
+    // edge tiles and the last K step load with bounds: elements outside the
+    // matrix read as +0, and no byte past a row's last element is read
     auto load_tiles = [&](int k0) {
+        const bool edge = !interior || k0 + GD_BK > K;
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
             int row, uc;
             a_unit_map<A_UPR>(t + GD_THREADS * i, row, uc);
-            load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + uc * U) * KIN), ra[i]);
+            const uint8_t* p = A + ((int64_t)(m0 + row) * lda + k0 + uc * U) * KIN;
+            if (!edge) load_dwords(reinterpret_cast<const uint32_t*>(p), ra[i]);
+            else gd_load_edge(p, m0 + row < M ? gd_clamp(K - (k0 + uc * U), U) * KIN : 0, ra[i]);
         }
 #pragma unroll
         for (int i = 0; i < B_UNITS; ++i) {
             const int u = t + GD_THREADS * i, row = u / B_UPR, uc = u % B_UPR;
-            load_dwords(reinterpret_cast<const uint32_t*>(B + ((int64_t)(k0 + row) * ldb + n0 + uc * U) * KIN), rb[i]);
+            const uint8_t* p = B + ((int64_t)(k0 + row) * ldb + n0 + uc * U) * KIN;
+            if (!edge) load_dwords(reinterpret_cast<const uint32_t*>(p), rb[i]);
+            else gd_load_edge(p, k0 + row < K ? gd_clamp(N - (n0 + uc * U), U) * KIN : 0, rb[i]);
         }
     };
     auto store_tiles = [&](int s) {
@@ -153,7 +189,7 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     };
 
     // the last K step is peeled so the loop body has no branches
-    const int KT = K / GD_BK;
+    const int KT = (K + GD_BK - 1) / GD_BK;
     load_tiles(0);
     store_tiles(0);
     __syncthreads();
@@ -182,43 +218,56 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                 g[0] = q;
 #pragma unroll
                 for (int e = 1; e < GO; ++e) g[e] = shfl_u64(q, (lane + e) % 64);
-                if (c16 % GO == 0) {
-                    uint32_t out[GO * KOUT / 4];
-                    assemble_elems<FO, GO>(g, out);
-                    store_dwords(reinterpret_cast<uint32_t*>(C + ((int64_t)row * ldc + col) * KOUT), out);
+                if (c16 % GO == 0 && (interior || (row < M && col < N))) {
+                    uint8_t* dst = C + ((int64_t)row * ldc + col) * KOUT;
+                    if (interior || col + GO <= N) {
+                        uint32_t out[GO * KOUT / 4];
+                        assemble_elems<FO, GO>(g, out);
+                        store_dwords(reinterpret_cast<uint32_t*>(dst), out);
+                    } else {
+                        // a group cut by the last column: bytes of its valid elements only
+#pragma unroll
+                        for (int e = 0; e < GO; ++e)
+                            if (col + e < N) store_elem_bytes<FO>(dst + e * KOUT, g[e]);
+                    }
                 }
             }
 }
 
 template <int KIN, int MODE>
 fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                            int64_t ldc, int M, int N, int K, hipStream_t stream)
+                     int64_t ldc, int M, int N, int K, const uint8_t* bandA, const uint8_t* bandB, hipStream_t stream)
 {
     auto a = static_cast<const uint8_t*>(A);
     auto b = static_cast<const uint8_t*>(B);
     auto c = static_cast<uint8_t*>(C);
+#define FLYTE_F64_LAUNCH(KO, MO) \
+    k_gemm_f64<KIN, KO, MO><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K, bandA, bandB)
     switch (kout) {
-        case 2: k_gemm_f64<KIN, 2, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 3: k_gemm_f64<KIN, 3, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 4: k_gemm_f64<KIN, 4, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 5: k_gemm_f64<KIN, 5, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 6: k_gemm_f64<KIN, 6, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        case 7: k_gemm_f64<KIN, 7, MODE><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
-        default: k_gemm_f64<KIN, 8, 0><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K); break;
+        case 2: FLYTE_F64_LAUNCH(2, MODE); break;
+        case 3: FLYTE_F64_LAUNCH(3, MODE); break;
+        case 4: FLYTE_F64_LAUNCH(4, MODE); break;
+        case 5: FLYTE_F64_LAUNCH(5, MODE); break;
+        case 6: FLYTE_F64_LAUNCH(6, MODE); break;
+        case 7: FLYTE_F64_LAUNCH(7, MODE); break;
+        default: FLYTE_F64_LAUNCH(8, 0); break;
     }
+#undef FLYTE_F64_LAUNCH
     return check_launch("fb_gemm");
 }
 
 // Runs C = A B for operands packed in {64, KIN} with C in the format fc (valid,
-// binary64); sizes already checked against the tile.  Instantiated per KIN in
-// its own source file so the instantiations compile in parallel.
+// binary64), any M, N, K >= 1 (edge tiles and the K tail are bounded); with
+// bandA/bandB only the flagged bands' tiles.  Instantiated per KIN in its own
+// source file so the instantiations compile in parallel.
 template <int KIN>
 fb_status gemm_f64_run(fb_format fc, unsigned blocks, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                       int64_t ldc, int M, int N, int K, hipStream_t stream)
+                       int64_t ldc, int M, int N, int K, const uint8_t* bandA, const uint8_t* bandB,
+                       hipStream_t stream)
 {
     return dispatch_round(fc, [&](auto rt) {
         constexpr int MODE = decltype(rt)::value;
-        return launch_f64<KIN, MODE>(fc.k, blocks, A, lda, B, ldb, C, ldc, M, N, K, stream);
+        return launch_f64<KIN, MODE>(fc.k, blocks, A, lda, B, ldb, C, ldc, M, N, K, bandA, bandB, stream);
     });
 }
 

@@ -4,8 +4,8 @@
 namespace flyte {
 
 template fb_status gemm_f64_run<5>(fb_format, unsigned, const void*, int64_t, const void*, int64_t, void*, int64_t,
-                                      int, int, int, hipStream_t);
+                                      int, int, int, const uint8_t*, const uint8_t*, hipStream_t);
 template fb_status gemm_f64_run<6>(fb_format, unsigned, const void*, int64_t, const void*, int64_t, void*, int64_t,
-                                      int, int, int, hipStream_t);
+                                      int, int, int, const uint8_t*, const uint8_t*, hipStream_t);
 
 }  // namespace flyte

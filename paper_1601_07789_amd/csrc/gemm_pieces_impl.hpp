@@ -1,0 +1,523 @@
+// GEMMs whose operands are split into bfloat16 pieces while they are staged
+// into LDS, on BF16 matrix cores with FP32 accumulation.
+//
+// The loader reads the packed k-byte elements as they are stored (4 elements,
+// k dwords, per load), turns each element into P bfloat16 pieces whose sum is
+// the element (or, for the default split products, its value to the stated
+// precision), and writes piece planes to LDS; the MFMA loop then forms the
+// products of pieces that the product set names, all into the same FP32
+// accumulators (Section 3.1: compute in the next type that holds the data;
+// Section 4.3: conversion is part of the load).
+//
+//  {32,2}: the stored pattern is a bfloat16 (one piece).
+//  {32,3}: hi = the top two bytes (a NaN gets the quiet bit, so it stays
+//    NaN), lo = x - hi rounded to bfloat16 (exact for biased exponent >= 9;
+//    0 for Inf/NaN).  Products hi*hi + hi*lo + lo*hi, or all four.
+//  {64,2}, {64,3}, {64,4} (5, 13 and 21 significant bits): the 11-bit
+//    exponent does not fit a bfloat16, so every row i of A and column j of B
+//    is scaled by an exact power of two, 2^-(e_i - 1023) and 2^-(e_j - 1023)
+//    with e the largest biased exponent in it, so its largest element lies in
+//    [1, 2); the scaled element is an exact binary32 value, cut into 1, 2 or 3
+//    bfloat16 pieces of 8, 8 and 5 bits (exact).  C_ij = 2^(e_i - 1023 + e_j -
+//    1023) * acc_ij in FP64, then cut to the output format.  A pass before the GEMM finds e_i, e_j and the rows and
+//    columns that cannot be scaled exactly (an element more than 2^40 below
+//    the largest, a binary64 subnormal, Inf or NaN); every 128 x 128 tile of C
+//    in a 128-row band of A or 128-column band of B holding such a row or
+//    column is recomputed by the FP64 matrix-core GEMM, which runs after this
+//    one on exactly those tiles.
+//
+// Tiling: BM x BN x 32 per workgroup, WGM x WGN waves each (BM/WGM) x
+// (BN/WGN) of v_mfma_f32_16x16x32_bf16 tiles; double-buffered LDS, one
+// barrier per K step, the next step's global loads issued before the current
+// step's MFMAs.  A is kept row-major in LDS and B n-major (k contiguous): a
+// thread loads 4 k-rows x 4 columns of B and transposes the pieces with
+// v_perm_b32, so every MFMA operand is one ds_read_b128.  LDS rows are
+// padded by 16 bytes.  Shapes need not be tile multiples: edge tiles and the
+// last K step load with bounds (elements outside the matrix read as +0, and
+// the bytes past a row's last element are never read), and C is stored only
+// inside the matrix.
+#pragma once
+
+#include "codec.hpp"
+#include "common.hpp"
+#include "gemm_pieces.hpp"
+
+namespace flyte {
+
+typedef __bf16 pc_bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 pc_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float pc_f32x4 __attribute__((ext_vector_type(4)));
+typedef float pc_f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t pc_u32x2 __attribute__((ext_vector_type(2)));
+
+constexpr int PC_BK = 32;            // K per stage: one MFMA
+constexpr int PC_ROW = PC_BK + 8;    // bfloat16 per padded LDS row
+constexpr int PC_SPREAD = 40;        // largest exponent spread a scaled row or column may have
+
+__host__ __device__ constexpr int pc_min(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int pc_max(int a, int b) { return a > b ? a : b; }
+
+// bfloat16 pair from two binary32 values, rounded to nearest even (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pc_cvt_pair(float a, float b)
+{
+    const pc_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, pc_bf16x2));
+}
+
+// top halves of two binary32 patterns (the bfloat16 values they are, when exact)
+__device__ __forceinline__ uint32_t pc_top_pair(uint32_t a, uint32_t b)
+{
+    return __builtin_amdgcn_perm(b, a, 0x07060302u);
+}
+
+// ---------------------------------------------------------------- loaders
+// A loader turns a chunk of 4 packed elements (KB dwords) into the binary32
+// patterns x[e] of their (scaled) values, and says how piece p of such a
+// value is formed: piece<p, SAFE>(x) is a binary32 pattern whose top half is
+// piece p, and ROUND_P (when set) marks the one piece that is paired by
+// rounding to nearest even (v_cvt_pk_bf16_f32) instead of taking top halves.
+// SAFE selects the handling of infinities and NaNs (only the {32,3} loader
+// has any); a wave takes the SAFE forms only when one of its elements of the
+// K step is not finite.  shift[e] (scaled formats): (e_ref - 127) << 20 of
+// the row or column of element e.
+
+struct PcB32K2 {
+    static constexpr int KB = 2, PIECES = 1, ROUND_P = -1;
+    static constexpr bool SCALED = false, RAW = true;   // the stored pairs are the piece pairs
+};
+
+struct PcB32K3 {
+    static constexpr int KB = 3, PIECES = 2, ROUND_P = 1;
+    static constexpr bool SCALED = false, RAW = false, SPECIALS = true;
+    __device__ static void values(const uint32_t (&d)[3], const int32_t (&)[4], uint32_t (&x)[4])
+    {
+        unpack_elems<Fmt<32, 3>, 4>(d, x);
+    }
+    // hi = the top two bytes (a NaN keeps its quiet bit set, so it stays NaN);
+    // lo = x - hi (exact in binary32), 0 for Inf/NaN
+    template <int PC, bool SAFE>
+    __device__ static uint32_t piece(uint32_t u)
+    {
+        if constexpr (PC == 0) {
+            if constexpr (SAFE) return ((u & 0x7FFFFFFFu) > 0x7F800000u) ? (u | 0x00400000u) : u;
+            return u;
+        } else {
+            const float lo = __uint_as_float(u) - __uint_as_float(u & 0xFFFF0000u);
+            if constexpr (SAFE) return ((u & 0x7F800000u) != 0x7F800000u) ? __float_as_uint(lo) : 0u;
+            return __float_as_uint(lo);
+        }
+    }
+};
+
+// {64,K}, K = 2..4: the scaled binary32 value of each element, then P = K - 1
+// pieces of it (8, 8 and 5 significant bits), all exact.
+template <int K>
+struct PcB64 {
+    static constexpr int KB = K, PIECES = K - 1, ROUND_P = -1;
+    static constexpr bool SCALED = true, RAW = false, SPECIALS = false;
+    __device__ static void values(const uint32_t (&d)[K], const int32_t (&shift)[4], uint32_t (&x)[4])
+    {
+        uint64_t u[4];
+        unpack_elems<Fmt<64, K>, 4>(d, u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t h = (uint32_t)(u[e] >> 32);   // sign, 11-bit exponent, top 20 mantissa bits
+            // exponent E -> E - e_ref + 127 in place (in [87, 127] for a row that
+            // can be scaled), then moved to binary32's 8-bit field
+            const uint32_t t = h - (uint32_t)shift[e];
+            const uint32_t f = (h & 0x80000000u) | ((t << 3) & 0x7FFFFFFFu);
+            x[e] = (h & 0x7FFFFFFFu) ? f : h;    // signed zeros stay zeros
+        }
+    }
+    template <int PC, bool SAFE>
+    __device__ static uint32_t piece(uint32_t f)
+    {
+        // the value minus its leading 8 bits, PC times (exact subtractions)
+        uint32_t r = f;
+#pragma unroll
+        for (int q = 0; q < PC; ++q) r = __float_as_uint(__uint_as_float(r) - __uint_as_float(r & 0xFFFF0000u));
+        return r;
+    }
+};
+
+// piece PC of two values as one bfloat16 pair
+template <class LD, int PC, bool SAFE>
+__device__ __forceinline__ uint32_t pc_pair(uint32_t a, uint32_t b)
+{
+    const uint32_t pa = LD::template piece<PC, SAFE>(a), pb = LD::template piece<PC, SAFE>(b);
+    if constexpr (PC == LD::ROUND_P) return pc_cvt_pair(__uint_as_float(pa), __uint_as_float(pb));
+    return pc_top_pair(pa, pb);
+}
+
+// Loads KB dwords of one 4-element chunk whose first nbytes bytes are valid
+// (0 <= nbytes <= 4 KB): dwords wholly inside are loaded, a straddling dword
+// is assembled from byte loads, the rest are zero.  Nothing past the valid
+// bytes is read.
+template <int KB>
+__device__ __forceinline__ void pc_load_edge(const uint8_t* p, int nbytes, uint32_t (&out)[KB])
+{
+#pragma unroll
+    for (int w = 0; w < KB; ++w) {
+        if (4 * w + 4 <= nbytes) {
+            out[w] = *reinterpret_cast<const uint32_t*>(p + 4 * w);
+        } else {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                if (4 * w + b < nbytes) v |= (uint32_t)p[4 * w + b] << (8 * b);
+            out[w] = v;
+        }
+    }
+}
+
+__device__ __forceinline__ void pc_tile_coords(int ntm, int ntn, int& tm, int& tn)
+{
+    const int nb = ntm * ntn;
+    int pid = blockIdx.x;
+    if (nb % 8 == 0) pid = (pid % 8) * (nb / 8) + pid / 8;   // consecutive tiles on one XCD
+    constexpr int GROUP = 8;
+    const int per_group = GROUP * ntn;
+    const int group = pid / per_group;
+    const int first_m = group * GROUP;
+    const int gsize = (ntm - first_m) < GROUP ? (ntm - first_m) : GROUP;
+    tm = first_m + (pid % per_group) % gsize;
+    tn = (pid % per_group) / gsize;
+}
+
+__device__ __forceinline__ uint64_t pc_shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src, 64);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// PRODS: bit (pa * P + pb) set = form the product of A piece pa and B piece pb.
+// OUTK = 0: C is FP32 (binary32 operands); else C is packed binary64 in OUTK
+// bytes, rounded in mode RMODE (scaled operands).
+// CHECK: loads and stores are bounded (any M, N, K); without it M, N are
+// multiples of BM, BN and K of 32.
+template <class LD, int PRODS, int BM, int BN, int WGM, int WGN, int OUTK, int RMODE, bool CHECK>
+__global__ void __launch_bounds__(64 * WGM * WGN)
+k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
+          void* __restrict__ Cv, int64_t ldc, int M, int N, int K, PcScale sc)
+{
+    constexpr int THREADS = 64 * WGM * WGN, P = LD::PIECES, KB = LD::KB;
+    constexpr int TM = BM / WGM, TN = BN / WGN, FM = TM / 16, FN = TN / 16;
+    constexpr int A_TILE = BM * PC_ROW, B_TILE = BN * PC_ROW, STAGE = P * (A_TILE + B_TILE);
+    constexpr int A_CH = BM * (PC_BK / 4) / THREADS;            // A chunks (4 elements of a row) per thread
+    constexpr int B_GR = (PC_BK / 4) * (BN / 4) / THREADS;      // B groups (4 k-rows x 4 columns) per thread
+    static_assert(A_CH * THREADS == BM * (PC_BK / 4) && A_CH >= 1, "A staging must divide evenly");
+    static_assert(B_GR * THREADS == (PC_BK / 4) * (BN / 4) && B_GR >= 1, "B staging must divide evenly");
+    static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile");
+    static_assert(STAGE * 2 * 2 <= 160 * 1024, "LDS");
+    static_assert(OUTK == 0 || LD::SCALED, "packed binary64 C comes from scaled operands");
+    // The accumulators go to AGPRs (an empty statement that clobbers one makes
+    // the compiler place them there), leaving the VGPRs to fragments and loads.
+    asm volatile("; accumulators in AGPRs" ::: "a0");
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2][STAGE];
+
+    const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+    int tm, tn;
+    pc_tile_coords(ntm, ntn, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+    if constexpr (LD::SCALED) {
+        // The FP64 GEMM that follows recomputes every 128 x 128 tile whose row
+        // band or column band is flagged; this tile is skipped only when all
+        // its 128 x 128 parts are such tiles.
+        const int b0 = m0 / 128, b1 = (pc_min(m0 + BM, M) - 1) / 128;
+        const int c0 = n0 / 128, c1 = (pc_min(n0 + BN, N) - 1) / 128;
+        bool rows = true, cols = true;
+        for (int b = b0; b <= b1; ++b) rows &= sc.bandA[b] != 0;
+        for (int b = c0; b <= c1; ++b) cols &= sc.bandB[b] != 0;
+        if (rows || cols) return;
+    }
+    const int t = threadIdx.x, lane = t % 64, wid = t / 64;
+    const int wm = wid / WGN, wn = wid % WGN;
+    const bool interior = !CHECK || (m0 + BM <= M && n0 + BN <= N);
+
+    // exponent shifts of this thread's A rows and B columns (fixed over K)
+    int32_t sa[A_CH][4], sb[B_GR][4];
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+        const int row = m0 + (t + THREADS * i) / (PC_BK / 4);
+        const int32_t v = (LD::SCALED && row < M) ? sc.shiftA[row] : 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sa[i][e] = v;
+    }
+#pragma unroll
+    for (int g = 0; g < B_GR; ++g) {
+        const int col = n0 + ((t + THREADS * g) % (BN / 4)) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sb[g][e] = (LD::SCALED && col + e < N) ? sc.shiftB[col + e] : 0;
+    }
+
+    uint32_t ra[A_CH][KB], rb[B_GR][4][KB];
+
+    // Byte offsets of this thread's chunks from the tile's corner, fixed over
+    // K: the per-step address is a wave-uniform base plus these (the host
+    // keeps BM * lda * KB and 32 * ldb * KB below 2^31 for the unchecked form).
+    uint32_t aoff[A_CH], boff[B_GR][4];
+#pragma unroll
+    for (int i = 0; i < A_CH; ++i) {
+        const int c = t + THREADS * i;
+        aoff[i] = (uint32_t)((c / (PC_BK / 4)) * lda * KB + (c % (PC_BK / 4)) * 4 * KB);
+    }
+#pragma unroll
+    for (int g = 0; g < B_GR; ++g) {
+        const int gi = t + THREADS * g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            boff[g][r] = (uint32_t)(((gi / (BN / 4)) * 4 + r) * ldb * KB + (gi % (BN / 4)) * 4 * KB);
+    }
+    const uint8_t* Atile = A + (int64_t)m0 * lda * KB;
+    const uint8_t* Btile = B + (int64_t)n0 * KB;
+
+    auto load_tiles = [&](int k0) {
+        const bool edge = CHECK && (!interior || k0 + PC_BK > K);
+        if (!edge) {
+            const uint8_t* Ak = Atile + k0 * KB;
+            const uint8_t* Bk = Btile + (int64_t)k0 * ldb * KB;
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) load_dwords(reinterpret_cast<const uint32_t*>(Ak + aoff[i]), ra[i]);
+#pragma unroll
+            for (int g = 0; g < B_GR; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) load_dwords(reinterpret_cast<const uint32_t*>(Bk + boff[g][r]), rb[g][r]);
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < A_CH; ++i) {
+            const int c = t + THREADS * i, row = m0 + c / (PC_BK / 4), kk = k0 + (c % (PC_BK / 4)) * 4;
+            const uint8_t* p = A + ((int64_t)row * lda + kk) * KB;
+            const int nv = row < M ? pc_max(0, pc_min(4, K - kk)) : 0;
+            pc_load_edge<KB>(p, nv * KB, ra[i]);
+        }
+#pragma unroll
+        for (int g = 0; g < B_GR; ++g) {
+            const int gi = t + THREADS * g, col = n0 + (gi % (BN / 4)) * 4, kr = k0 + (gi / (BN / 4)) * 4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint8_t* p = B + ((int64_t)(kr + r) * ldb + col) * KB;
+                const int nv = kr + r < K ? pc_max(0, pc_min(4, N - col)) : 0;
+                pc_load_edge<KB>(p, nv * KB, rb[g][r]);
+            }
+        }
+    };
+
+    auto store_tiles = [&](int s) {
+        uint16_t* As = lds[s];
+        uint16_t* Bs = lds[s] + P * A_TILE;
+        if constexpr (LD::RAW) {
+            // bfloat16 operands: A chunks are already pairs along k; B rows are
+            // transposed pairwise into pairs along k
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) {
+                const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
+                *reinterpret_cast<pc_u32x2*>(As + row * PC_ROW + kc * 4) = pc_u32x2{ra[i][0], ra[i][1]};
+            }
+#pragma unroll
+            for (int g = 0; g < B_GR; ++g) {
+                const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const uint32_t sel = (c % 2) ? 0x07060302u : 0x05040100u;
+                    const uint32_t d0 = __builtin_amdgcn_perm(rb[g][1][c / 2], rb[g][0][c / 2], sel);
+                    const uint32_t d1 = __builtin_amdgcn_perm(rb[g][3][c / 2], rb[g][2][c / 2], sel);
+                    *reinterpret_cast<pc_u32x2*>(Bs + (nc + c) * PC_ROW + kg * 4) = pc_u32x2{d0, d1};
+                }
+            }
+        } else {
+            uint32_t xa[A_CH][4], xb[B_GR][4][4];   // values: A [chunk][element], B [group][k-row][column]
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) LD::values(ra[i], sa[i], xa[i]);
+#pragma unroll
+            for (int g = 0; g < B_GR; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) LD::values(rb[g][r], sb[g], xb[g][r]);
+            // piece pairs: A along its chunk, B down its 4 k-rows
+            auto a_pair = [&](auto ip, auto safe, int i, int h) {
+                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xa[i][2 * h], xa[i][2 * h + 1]);
+            };
+            auto b_pair = [&](auto ip, auto safe, int g, int c, int h) {
+                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][2 * h][c], xb[g][2 * h + 1][c]);
+            };
+            auto put = [&](auto safe) {
+#pragma unroll
+                for (int i = 0; i < A_CH; ++i) {
+                    const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
+                    static_for<P>([&](auto ip) {
+                        constexpr int p = decltype(ip)::value;
+                        *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + row * PC_ROW + kc * 4) =
+                            pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
+                    });
+                }
+#pragma unroll
+                for (int g = 0; g < B_GR; ++g) {
+                    const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        static_for<P>([&](auto ip) {
+                            constexpr int p = decltype(ip)::value;
+                            *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + (nc + c) * PC_ROW + kg * 4) =
+                                pc_u32x2{b_pair(ip, safe, g, c, 0), b_pair(ip, safe, g, c, 1)};
+                        });
+                }
+            };
+            if constexpr (LD::SPECIALS) {
+                // A wave takes the forms that handle Inf and NaN only when one of
+                // its values of this step is one (a wave-uniform branch).  The test
+                // runs on the piece-0 pairs (top halves): a half shifted left by one
+                // is at least 0xFF00 exactly when its exponent field is all ones.
+                typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+                u16x2_t mx = {0, 0};
+#pragma unroll
+                for (int i = 0; i < A_CH; ++i)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+                        mx = __builtin_elementwise_max(
+                            mx, __builtin_bit_cast(u16x2_t, a_pair(std::integral_constant<int, 0>{}, std::false_type{}, i, h) << 1));
+#pragma unroll
+                for (int g = 0; g < B_GR; ++g)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            mx = __builtin_elementwise_max(
+                                mx, __builtin_bit_cast(u16x2_t,
+                                                       b_pair(std::integral_constant<int, 0>{}, std::false_type{}, g, c, h) << 1));
+                const bool special = mx.x >= 0xFF00 || mx.y >= 0xFF00;
+                if (__builtin_amdgcn_ballot_w64(special)) put(std::true_type{});
+                else put(std::false_type{});
+            } else {
+                put(std::false_type{});
+            }
+        }
+    };
+
+    pc_f32x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) acc[i][j] = pc_f32x4{0.f, 0.f, 0.f, 0.f};
+
+    auto compute = [&](int s) {
+        const int r16 = lane % 16, kq = 8 * (lane / 16);
+        pc_bf16x8 a[P][FM], b[P][FN];
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + (wm * TM + i * 16 + r16) * PC_ROW + kq);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE +
+                                                              (wn * TN + j * 16 + r16) * PC_ROW + kq);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                static_for<P * P>([&](auto iq) {
+                    constexpr int q = decltype(iq)::value;
+                    if constexpr ((PRODS >> q) & 1)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[q / P][i], b[q % P][j], acc[i][j], 0, 0, 0);
+                });
+        __builtin_amdgcn_s_setprio(0);
+    };
+
+    // the last K step is peeled so the loop body has no branches on it
+    const int KT = (K + PC_BK - 1) / PC_BK;
+    load_tiles(0);
+    store_tiles(0);
+    __syncthreads();
+    for (int kt = 0; kt < KT - 1; ++kt) {
+        const int s = kt & 1;
+        load_tiles((kt + 1) * PC_BK);
+        // the next step's global loads stay ahead of this step's MFMAs
+        __builtin_amdgcn_sched_barrier(0);
+        compute(s);
+        store_tiles(s ^ 1);
+        __syncthreads();
+    }
+    compute((KT - 1) & 1);
+
+    // ---- epilogue: lane holds rows 4 * (lane / 16) + r, column lane % 16 of each 16 x 16 tile
+    if constexpr (OUTK == 0) {
+        float* C = static_cast<float*>(Cv);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * TM + i * 16 + 4 * (lane / 16) + r;
+                    const int col = n0 + wn * TN + j * 16 + lane % 16;
+                    if (interior || (row < M && col < N)) C[(int64_t)row * ldc + col] = acc[i][j][r];
+                }
+    } else {
+        // C_ij = 2^(e_i - 1023 + e_j - 1023) acc_ij in FP64 (exact), cut to OUTK bytes;
+        // the G lanes of a dword-aligned group of columns hand their packed
+        // values to the group's first lane, which stores whole dwords (or, for a
+        // group cut by the last column, the bytes of its valid elements)
+        using FO = Fmt<64, OUTK>;
+        constexpr int GO = FO::G;
+        uint8_t* C = static_cast<uint8_t*>(Cv);
+        const int c16 = lane % 16;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int col = n0 + wn * TN + j * 16 + c16;
+            // the scaled value of an element is 2^-(e_ref - 1023) times it
+            const int ec = (col < N) ? (sc.shiftB[col] >> 20) - 896 : 0;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = m0 + wm * TM + i * 16 + 4 * (lane / 16) + r;
+                    const int er = (row < M) ? (sc.shiftA[row] >> 20) - 896 : 0;
+                    const double v = __builtin_amdgcn_ldexp((double)acc[i][j][r], er + ec);
+                    const uint64_t q = round_pack<FO, RMODE>((uint64_t)__double_as_longlong(v));
+                    uint64_t gq[GO];
+                    gq[0] = q;
+#pragma unroll
+                    for (int e = 1; e < GO; ++e) gq[e] = pc_shfl_u64(q, (lane + e) % 64);
+                    if (c16 % GO == 0 && row < M && col < N) {
+                        uint8_t* dst = C + ((int64_t)row * ldc + col) * OUTK;
+                        if (col + GO <= N) {
+                            uint32_t out[GO * OUTK / 4];
+                            assemble_elems<FO, GO>(gq, out);
+                            store_dwords(reinterpret_cast<uint32_t*>(dst), out);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < GO; ++e)
+                                if (col + e < N) store_elem_bytes<FO>(dst + e * OUTK, gq[e]);
+                        }
+                    }
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+template <class LD, int PRODS, int BM, int BN, int WGM, int WGN, int OUTK, int RMODE>
+fb_status pc_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        void* C, int64_t ldc, const PcScale& sc, hipStream_t stream)
+{
+    const int64_t blocks = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    auto a = static_cast<const uint8_t*>(A);
+    auto b = static_cast<const uint8_t*>(B);
+    // shapes that are tile multiples (and whose per-tile offsets fit 31 bits)
+    // take the instance without bounds checks
+    constexpr int KB = LD::KB;
+    if (M % BM == 0 && N % BN == 0 && K % PC_BK == 0 && (int64_t)BM * lda * KB < (1ll << 31) &&
+        (int64_t)PC_BK * ldb * KB < (1ll << 31))
+        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, false><<<(unsigned)blocks, 64 * WGM * WGN, 0, stream>>>(
+            a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
+    else
+        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, true><<<(unsigned)blocks, 64 * WGM * WGN, 0, stream>>>(
+            a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
+    return check_launch("fb_gemm");
+}
+
+}  // namespace flyte

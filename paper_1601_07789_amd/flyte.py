@@ -414,7 +414,9 @@ class BatchedGemv:
 
 
 # ---------------------------------------------------------------- BLAS 3
-GEMM_FOUR_PRODUCTS = 1
+GEMM_ALL_PRODUCTS = 1
+GEMM_FOUR_PRODUCTS = 1    # the {32,3} name of GEMM_ALL_PRODUCTS
+GEMM_FP64 = 2
 
 
 def gemm(fa, fb, fc, M: int, N: int, K: int, A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None,

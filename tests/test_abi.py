@@ -98,27 +98,34 @@ def test_gemv_argument_errors(lib):
 
 
 def test_gemm_argument_errors(lib):
+    # every call below fails validation before anything is launched (the
+    # pointers are never dereferenced)
     args = (128, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128, None)
     assert lib.fb_gemm(F(32, 2), F(32, 3), F(32, 4), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(64, 7), F(32, 2), F(64, 7), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(64, 3), F(64, 3), F(32, 4), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(32, 2), F(32, 2), F(64, 8), *args) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm(F(64, 5), F(64, 6), F(64, 5), *args) == flyte.FB_ERR_UNSUPPORTED
-    assert lib.fb_gemm(F(32, 2), F(32, 2), F(32, 4), 100, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128,
-                       None) == flyte.FB_ERR_UNSUPPORTED                                     # M not a tile multiple
-    assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 128, 128, 24, FAKE, 24, FAKE, 128, FAKE, 128,
-                       None) == flyte.FB_ERR_UNSUPPORTED                                     # K not a multiple of 16
     assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 128, 128, 64, FAKE, 32, FAKE, 128, FAKE, 128,
                        None) == flyte.FB_ERR_ARG                                             # lda < K
     assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 128, 128, 64, MISALIGNED, 64, FAKE, 128, FAKE, 128,
                        None) == flyte.FB_ERR_ALIGN
+    assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 128, 128, 3, FAKE, 3, FAKE, 128, FAKE, 128,
+                       None) == flyte.FB_ERR_ALIGN                                           # 15-byte rows of A
+    assert lib.fb_gemm(F(32, 3), F(32, 3), F(32, 4), 5, 7, 9, FAKE, 9, FAKE, 8, FAKE, 7,
+                       None) == flyte.FB_ERR_ALIGN                                           # 27-byte rows of A
     assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 0, 128, 64, None, 64, None, 128, None, 128,
                        None) == flyte.FB_OK
+    assert lib.fb_gemm(F(64, 5), F(64, 5), F(64, 5), 128, 128, 64, None, 64, FAKE, 128, FAKE, 128,
+                       None) == flyte.FB_ERR_ARG                                             # null A
+    assert lib.fb_gemm(F(32, 2), F(32, 2), F(32, 4), -1, 128, 64, FAKE, 64, FAKE, 128, FAKE, 128,
+                       None) == flyte.FB_ERR_ARG                                             # negative M
+    # flags: all products only for split operands; FP64 only for binary64; unknown bits
     assert lib.fb_gemm_ex(F(32, 2), F(32, 2), F(32, 4), *args[:-1], 1, None) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm_ex(F(64, 5), F(64, 5), F(64, 5), *args[:-1], 1, None) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm_ex(F(64, 3), F(64, 3), F(64, 3), *args[:-1], 3, None) == flyte.FB_ERR_UNSUPPORTED
+    assert lib.fb_gemm_ex(F(32, 3), F(32, 3), F(32, 4), *args[:-1], 2, None) == flyte.FB_ERR_UNSUPPORTED
     assert lib.fb_gemm_ex(F(32, 3), F(32, 3), F(32, 4), *args[:-1], 4, None) == flyte.FB_ERR_ARG
-    big_n = 65536 * 64     # the split pass of {32,3} B puts N/64 tiles on one grid axis
-    assert lib.fb_gemm(F(32, 3), F(32, 3), F(32, 4), 128, big_n, 64, FAKE, 64, FAKE, big_n, FAKE, big_n,
-                       None) == flyte.FB_ERR_UNSUPPORTED
 
 
 def test_batched_plan_rejects_bad_descriptor(lib):

@@ -5,9 +5,14 @@ Error measures (componentwise-normwise, so near-zero entries do not blow up):
 Bounds (K inner dimension, u32 = 2^-24, u64 = 2^-53, gamma_n(u) = n u / (1 - n u)):
   BF16 ({32,2}):      products exact in FP32        -> e1 <= gamma_K(u32)
   3-product ({32,3}): |lo| < 2^-7 |x|, lo*lo dropped -> e1 <= 2^-14 + gamma_3K(u32) (1 + 2^-7)^2
+  4-product:          every product exact          -> e1 <= gamma_4K(u32) (1 + 2^-7)^2
   FP64 ({64,2..8}):   |unpack(C) - C*| <= gamma_K(u64) (|A||B|) + 2^-(m+1) (|C*| + gamma_K(u64) (|A||B|))
-Integer-valued FP64 data is exact in FP64, so its packed C must equal the
-oracle's pack of the exact product bit for bit.
+  scaled pieces ({64,2..4} on BF16 matrix cores, P = k - 1 pieces of 8, 8, 5 bits,
+  |piece_i| < 2^-7i |x|): e1 <= drop + gamma_{nK}(u32) (1 + 2^-7 + 2^-14)^2, n the
+  number of products formed (1; 3 or 4; 6 or 9), drop the bound of the products
+  left out (0; 2^-14; 2^-20 (1 + 2^-8)), then the cut to the output format.
+Integer-valued data whose products and sums are exact in the accumulation
+type must give C (or the oracle's pack of it) bit for bit.
 """
 from __future__ import annotations
 
@@ -123,8 +128,8 @@ def test_gemm_f64_integer_data_bit_exact(dev, orc):
 @pytest.mark.parametrize("kin,kout", [(5, 5), (6, 6), (5, 8), (6, 3), (2, 2), (3, 3), (4, 4), (2, 8), (4, 6), (7, 7),
                                       (8, 8), (8, 5)])
 def test_gemm_f64_random_all_entries(dev, orc, kin, kout):
-    """Rows of A scaled over 2^-300 .. 2^300: the full binary64 exponent range of
-    the narrow formats, beyond what a bfloat16 split could carry."""
+    """The FP64 matrix-core path (the only one for k >= 5; FB_GEMM_FP64 for k <= 4),
+    rows of A scaled over 2^-300 .. 2^300: the full binary64 exponent range."""
     import torch
     log(f"gemm f64 {kin}->{kout}")
     M, N, K = 128, 256, 208
@@ -132,7 +137,8 @@ def test_gemm_f64_random_all_entries(dev, orc, kin, kout):
     Av = g.standard_normal((M, K)) * np.exp2(np.round(g.uniform(-300, 300, (M, 1))))
     Bv = g.standard_normal((K, N))
     A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
-    C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev))
+    C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+                   flags=flyte.GEMM_FP64)
     Cu = orc.unpack(64, kout, C.cpu().numpy().view(np.uint8)) if kout < 8 else C.cpu().numpy()
     ii, jj = all_entries(M, N)
     ce, cab = orc.gemm_entries((64, kin), (64, kin), K, A, K, B, N, ii, jj)
@@ -209,7 +215,7 @@ def test_gemm_f64_benchmark_size_sampled(dev, orc, k):
     v.normal_(generator=g)
     B = flyte.pack((64, k), v)
     del v
-    C = flyte.gemm((64, k), (64, k), (64, k), n, n, n, A, B)
+    C = flyte.gemm((64, k), (64, k), (64, k), n, n, n, A, B, flags=flyte.GEMM_FP64 if k <= 4 else 0)
     torch.cuda.synchronize()
     Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
     ii, jj, ce, cab = sampled(orc, (64, k), n, Ah, Bh, n, None, n, 4, count=128)
@@ -341,3 +347,182 @@ def test_gemm_padded_leading_dimensions(dev, orc, case):
     bound = {"bf16": gam(K, U32), "three": 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2,
              "four": gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2, "f64": gam(K, U64)}[case]
     assert e1 <= bound, (e1, bound)
+
+
+# ---------------------------------------------------------------- shapes that are not tile multiples
+def _ld(n, k):
+    g = {1: 4, 2: 2, 3: 4, 4: 1, 5: 4, 6: 2, 7: 4, 8: 1}[k]
+    return (n + g - 1) // g * g        # rows start 4-byte aligned
+
+
+RAGGED = [(300, 310, 277), (1, 5, 3), (129, 257, 65), (300, 200, 4), (257, 131, 1)]
+
+
+@pytest.mark.parametrize("case", ["bf16", "three", "four"])
+@pytest.mark.parametrize("shape", RAGGED)
+def test_gemm_ragged_binary32(dev, orc, case, shape):
+    """M, N, K not tile multiples (and K below one step): every entry within the
+    bound, C's padding columns untouched."""
+    import torch
+    log(f"gemm ragged {case} {shape}")
+    M, N, K = shape
+    k = 2 if case == "bf16" else 3
+    lda, ldb, ldc = _ld(K, k) + (4 if k == 3 else 2), _ld(N, k), N + 3
+    g = np.random.default_rng(M * 7 + N + K)
+    A = orc.pack(32, k, g.standard_normal(M * lda).astype(np.float32))
+    B = orc.pack(32, k, g.standard_normal(K * ldb).astype(np.float32))
+    C = torch.full((M * ldc,), 7.0, dtype=torch.float32, device=dev)
+    flyte.gemm((32, k), (32, k), (32, 4), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), C=C,
+               lda=lda, ldb=ldb, ldc=ldc, flags=flyte.GEMM_ALL_PRODUCTS if case == "four" else 0)
+    Ch = C.cpu().numpy().reshape(M, ldc).astype(np.float64)
+    assert np.all(Ch[:, N:] == 7.0)
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((32, k), (32, k), K, A, lda, B, ldb, ii, jj)
+    bound = {"bf16": gam(K, U32), "three": 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2,
+             "four": gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2}[case]
+    assert np.all(np.abs(Ch[:, :N].reshape(-1) - ce) <= bound * cab)
+
+
+@pytest.mark.parametrize("kin,kout", [(5, 5), (6, 8), (8, 3), (3, 7)])
+@pytest.mark.parametrize("shape", [(300, 520, 333), (129, 1, 17), (1, 130, 250)])
+def test_gemm_ragged_f64(dev, orc, kin, kout, shape):
+    """The FP64 path at shapes that are not tile multiples: every entry within the
+    bound, bytes of C outside the M x N block untouched."""
+    import torch
+    log(f"gemm ragged f64 {kin}->{kout} {shape}")
+    M, N, K = shape
+    lda, ldb, ldc = _ld(K, kin) + 4, _ld(N, kin), _ld(N, kout) + 4
+    g = np.random.default_rng(kin * 31 + kout + M)
+    A = orc.pack(64, kin, g.standard_normal(M * lda))
+    B = orc.pack(64, kin, g.standard_normal(K * ldb))
+    C = torch.full((M * ldc * kout,), 0x5A, dtype=torch.uint8, device=dev)
+    flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev),
+               C=C if kout < 8 else C.view(torch.float64), lda=lda, ldb=ldb, ldc=ldc, flags=flyte.GEMM_FP64)
+    Ch = C.cpu().numpy().reshape(M, ldc * kout)
+    assert np.all(Ch[:, N * kout:] == 0x5A)
+    Cu = orc.unpack(64, kout, np.ascontiguousarray(Ch[:, :N * kout]).reshape(-1))
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((64, kin), (64, kin), K, A, lda, B, ldb, ii, jj)
+    m = 8 * kout - 12
+    bound = gam(K, U64) * cab + 2.0 ** -(m + 1) * (np.abs(ce) + gam(K, U64) * cab)
+    assert np.all(np.abs(Cu - ce) <= bound * (1 + 1e-12))
+
+
+# ---------------------------------------------------------------- binary64 k <= 4 on bfloat16 pieces
+def pieces_bound(kin, allp, K, ce, cab, kout):
+    P = kin - 1
+    n = P * P if allp else {1: 1, 2: 3, 3: 6}[P]
+    drop = 0.0 if (allp or P == 1) else (2.0 ** -14 if P == 2 else 2.0 ** -20 * (1 + 2.0 ** -8))
+    e = drop + gam(n * K, U32) * (1 + 2.0 ** -7 + 2.0 ** -14) ** 2
+    m = 8 * kout - 12
+    return e * cab + 2.0 ** -(m + 1) * (np.abs(ce) + e * cab)
+
+
+@pytest.mark.parametrize("kin", [2, 3, 4])
+@pytest.mark.parametrize("allp", [False, True])
+@pytest.mark.parametrize("shape", [(256, 256, 128), (300, 264, 133), (384, 256, 64)])
+def test_gemm_pieces_all_entries(dev, orc, kin, allp, shape):
+    """Rows of A scaled over 2^-300 .. 2^300 and columns of B over 2^-200 .. 2^200
+    (each row or column scales as a whole, exactly): every entry within the pieces
+    bound, for a native and two packed output formats."""
+    import torch
+    log(f"gemm pieces k={kin} all={allp} {shape}")
+    M, N, K = shape
+    lda, ldb = _ld(K, kin), _ld(N, kin)
+    g = np.random.default_rng(kin * 100 + M + N)
+    Av = g.standard_normal((M, lda)) * np.exp2(np.round(g.uniform(-300, 300, (M, 1))))
+    Bv = g.standard_normal((K, ldb)) * np.exp2(np.round(g.uniform(-200, 200, (1, ldb))))
+    A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((64, kin), (64, kin), K, A, lda, B, ldb, ii, jj)
+    for kout in (8, kin, 5):
+        C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, Ad, Bd, lda=lda, ldb=ldb,
+                       flags=flyte.GEMM_ALL_PRODUCTS if allp else 0).cpu().numpy()
+        Cu = orc.unpack(64, kout, C.view(np.uint8)) if kout < 8 else C
+        err = np.abs(Cu.reshape(-1) - ce)
+        assert np.all(err <= pieces_bound(kin, allp, K, ce, cab, kout) * (1 + 1e-9)), (kout, np.max(err / cab))
+
+
+@pytest.mark.parametrize("kin", [2, 3, 4])
+def test_gemm_pieces_integer_data_bit_exact(dev, orc, kin):
+    """Small integers: every product of pieces and every FP32 partial sum is exact
+    (|C| < 2^24), so the packed C must equal the oracle's pack of the exact product
+    bit for bit, in every output format and with either product set."""
+    import torch
+    log(f"gemm pieces integers k={kin}")
+    M, N, K = 256, 256, 192
+    g = np.random.default_rng(60 + kin)
+    lim = 31 if kin == 2 else 64
+    Av = g.integers(-lim, lim + 1, (M, K)).astype(np.float64)
+    Bv = g.integers(-lim, lim + 1, (K, N)).astype(np.float64)
+    exact = Av @ Bv
+    A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    for flags in (0, flyte.GEMM_ALL_PRODUCTS):
+        for kout in (2, 3, 4, 5, 8):
+            C = flyte.gemm((64, kin), (64, kin), (64, kout), M, N, K, Ad, Bd, flags=flags).cpu().numpy()
+            want = orc.pack(64, kout, exact.reshape(-1))
+            assert np.array_equal(C if kout < 8 else C.view(np.uint8), want), (flags, kout)
+
+
+@pytest.mark.parametrize("kin", [3, 4])
+def test_gemm_pieces_fallback_bands(dev, orc, kin):
+    """Rows and columns that cannot be scaled exactly -- an element 2^-60 below its
+    row's largest, a binary64 subnormal, an infinity, a NaN -- send every 128 x 128
+    tile of their band to the FP64 matrix cores: those tiles equal the FP64 path's
+    result bit for bit, the others meet the pieces bound, and the special values
+    propagate exactly (infinities stay infinities here)."""
+    import torch
+    log(f"gemm pieces fallback k={kin}")
+    M, N, K = 640, 512, 64
+    g = np.random.default_rng(70 + kin)
+    Av = g.standard_normal((M, K))
+    Bv = g.standard_normal((K, N))
+    Av[5, 3] *= 2.0 ** -60          # row band 0 of A: spread above 2^40
+    Av[300, 7] = 5e-310             # row band 2: a binary64 subnormal
+    Bv[9, 200] = np.inf             # column band 1 of B: infinity
+    Bv[20, 450] = np.nan            # column band 3: NaN
+    A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
+    Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
+    C = flyte.gemm((64, kin), (64, kin), (64, 8), M, N, K, Ad, Bd).cpu().numpy().reshape(M, N)
+    F = flyte.gemm((64, kin), (64, kin), (64, 8), M, N, K, Ad, Bd, flags=flyte.GEMM_FP64).cpu().numpy().reshape(M, N)
+    band_a = np.zeros(M // 128, bool)
+    band_a[[0, 2]] = True
+    band_b = np.zeros(N // 128, bool)
+    band_b[[1, 3]] = True
+    fb = band_a[np.arange(M) // 128][:, None] | band_b[np.arange(N) // 128][None, :]
+    assert np.array_equal(C[fb].view(np.uint64), F[fb].view(np.uint64))
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((64, kin), (64, kin), K, A, K, B, N, ii, jj)
+    ce, cab = ce.reshape(M, N), cab.reshape(M, N)
+    ok = ~fb
+    assert np.all(np.abs(C[ok] - ce[ok]) <= pieces_bound(kin, False, K, ce[ok], cab[ok], 8) * (1 + 1e-9))
+    assert np.all(np.isnan(C[np.isnan(ce)]))
+    inf = np.isinf(ce)
+    assert inf.sum() > 0 and np.array_equal(C[inf], ce[inf])
+
+
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_gemm_pieces_benchmark_size_sampled(dev, orc, k):
+    """M = N = K = 16384, N(0,1) entries packed to {64,k}, C packed to the same k on
+    the bfloat16 pieces: sampled entries within the pieces bound."""
+    import torch
+    log(f"gemm pieces k={k} 16384^3 sampled")
+    n = 16384
+    g = torch.Generator(device=dev)
+    g.manual_seed(workloads.SEED_BASE + 4)
+    v = torch.empty(n * n, dtype=torch.float64, device=dev).normal_(generator=g)
+    A = flyte.pack((64, k), v)
+    v.normal_(generator=g)
+    B = flyte.pack((64, k), v)
+    del v
+    C = flyte.gemm((64, k), (64, k), (64, k), n, n, n, A, B)
+    torch.cuda.synchronize()
+    Ah, Bh = A.cpu().numpy(), B.cpu().numpy()
+    ii, jj, ce, cab = sampled(orc, (64, k), n, Ah, Bh, n, None, n, 5, count=128)
+    idx = torch.from_numpy(((ii * n + jj)[:, None] * k + np.arange(k)[None, :]).reshape(-1)).to(dev)
+    got = orc.unpack(64, k, C[idx].cpu().numpy())
+    assert np.all(np.abs(got - ce) <= pieces_bound(k, False, n, ce, cab, k) * (1 + 1e-9))
+    del A, B, C
+    torch.cuda.empty_cache()

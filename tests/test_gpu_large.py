@@ -135,7 +135,7 @@ def test_gemv_transposed_past_4gib_exact(dev, orc):
     assert same_bits(y, torch.from_numpy(yt.astype(np.float64)).to(dev))
 
 
-@pytest.mark.parametrize("f,size", [((32, 2), 49152), ((32, 3), 49152), ((64, 5), 32768)])
+@pytest.mark.parametrize("f,size", [((32, 2), 49152), ((32, 3), 49152), ((64, 3), 49152), ((64, 5), 32768)])
 def test_gemm_past_4gib_exact(dev, orc, f, size):
     """A and B (more than 4 GiB each) repeat 64 x 64 and 64 x N integer blocks, so C
     repeats a 64 x N block of integers that every product and partial sum represents
