@@ -656,7 +656,8 @@ def gemm_errors(orc, np, fa, fc, M, N, K, Ah, Bh, C_rows, rows, exact_entries=12
 
 def bench_gemm(flyte, workloads, torch, np, dev, stream, oracle_times):
     """TFLOP/s of the GEMM paths (2*M*N*K useful flop per call; median of 10 calls at
-    8192^3, 3 at 16384^3), their errors e1, e2, e3 on sampled rows, the vendor
+    8192^3, 3 at 16384^3; binary64 k = 2..4 both on bfloat16 pieces and on FP64
+    matrix cores), their errors e1, e2, e3 on sampled rows, the vendor
     library's bfloat16 and FP64 GEMMs at the same sizes beside them, and with the
     oracle: its naive GEMM timed on a block of rows on all host threads, the full
     time extrapolated from it."""
@@ -712,25 +713,36 @@ def bench_gemm(flyte, workloads, torch, np, dev, stream, oracle_times):
     g.manual_seed(workloads.SEED_BASE + 4)
     Mf = 16384
     rows_f = [0, Mf - 1] + [int(r) for r in rng.integers(1, Mf - 1, 2)]
-    for k in (5, 6, 3):
-        Av = torch.empty(Mf * Mf, dtype=torch.float64, device=dev).normal_(generator=g)
-        Ap = flyte.pack((64, k), Av)
-        Av.normal_(generator=g)
-        Bp = flyte.pack((64, k), Av)
-        del Av
-        C = torch.empty(Mf * Mf * k, dtype=torch.uint8, device=dev)
-        ms = median_ms(torch, stream, lambda: flyte.gemm((64, k), (64, k), (64, k), Mf, Mf, Mf, Ap, Bp, C), 3,
-                       warm=1)
-        entry = {"M": Mf, "N": Mf, "K": Mf, "ms": round(ms, 2), "TFLOPs": tf(Mf, ms)}
-        Ah, Bh = Ap.cpu().numpy(), Bp.cpu().numpy()
+    # binary64 k = 5, 6 on FP64 matrix cores; k = 2, 3, 4 on bfloat16 pieces (the
+    # default) and, beside them, on FP64 matrix cores (FB_GEMM_FP64)
+    runs = [(5, "fp64_k5", 0), (6, "fp64_k6", 0), (3, "fp64_k3", flyte.GEMM_FP64), (3, "pieces_k3", 0),
+            (2, "fp64_k2", flyte.GEMM_FP64), (2, "pieces_k2", 0), (4, "fp64_k4", flyte.GEMM_FP64), (4, "pieces_k4", 0)]
+    cur = None
+    for k, name, flags in runs:
+        if cur != k:
+            Ap = Bp = Ah = Bh = None
+            torch.cuda.empty_cache()
+            Av = torch.empty(Mf * Mf, dtype=torch.float64, device=dev).normal_(generator=g)
+            Ap = flyte.pack((64, k), Av)
+            Av.normal_(generator=g)
+            Bp = flyte.pack((64, k), Av)
+            del Av
+            C = torch.empty(Mf * Mf * k, dtype=torch.uint8, device=dev)
+            Ah, Bh = Ap.cpu().numpy(), Bp.cpu().numpy()
+            cur = k
+        ms = median_ms(torch, stream, lambda: flyte.gemm((64, k), (64, k), (64, k), Mf, Mf, Mf, Ap, Bp, C, flags=flags),
+                       3, warm=1)
+        entry = {"M": Mf, "N": Mf, "K": Mf, "ms": round(ms, 2), "TFLOPs": tf(Mf, ms),
+                 "path": "bfloat16 pieces" if name.startswith("pieces") else "FP64 matrix cores"}
         Cb = C.view(Mf, Mf * k)[torch.tensor(rows_f, device=dev)].cpu().numpy()
         C_rows = np.stack([orc.unpack(64, k, Cb[t]) for t in range(len(rows_f))])
         entry["errors"], _ = gemm_errors(orc, np, (64, k), (64, k), Mf, Mf, Mf, Ah, Bh, C_rows, rows_f)
         entry["errors"]["c_format_half_ulp"] = 2.0 ** -(8 * k - 12 + 1)
-        out[f"fp64_k{k}"] = entry
-        if oracle_times is not None and k in (5, 6):
+        out[name] = entry
+        if oracle_times is not None and name in ("fp64_k5", "fp64_k6"):
             oracle_times[f"gemm_b64_k{k}"] = oracle_block((64, k), Mf, Mf, Mf, Ah, Bh, nth)
-        del Ap, Bp, C, Ah, Bh
+    del Ap, Bp, C, Ah, Bh
+    torch.cuda.empty_cache()
     # the vendor library's FP64 GEMM at the same size (native FP64 operands and C)
     a64 = torch.empty(Mf, Mf, dtype=torch.float64, device=dev).normal_(generator=g)
     b64 = torch.empty(Mf, Mf, dtype=torch.float64, device=dev).normal_(generator=g)
