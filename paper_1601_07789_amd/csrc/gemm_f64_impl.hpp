@@ -94,8 +94,9 @@ __device__ __forceinline__ int gd_clamp(int v, int hi) { return v < 0 ? 0 : (v >
 
 // bandA, bandB (may be null): when given, only the tiles whose 128-row band of
 // A or 128-column band of B is flagged are computed (the rest belong to the
-// bfloat16-piece GEMM of the same call).
-template <int KIN, int KOUT, int MODE>
+// bfloat16-piece GEMM of the same call).  CHECK: loads and stores are bounded
+// (any M, N, K); without it M, N are multiples of 128 and K of 16.
+template <int KIN, int KOUT, int MODE, bool CHECK>
 __global__ void __launch_bounds__(GD_THREADS, 2)
 k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            uint8_t* __restrict__ C, int64_t ldc, int M, int N, int K, const uint8_t* __restrict__ bandA,
@@ -116,7 +117,7 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     const int m0 = tm * GD_BM, n0 = tn * GD_BN;
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
     const int wm = wid / 2, wn = wid % 2;
-    const bool interior = m0 + GD_BM <= M && n0 + GD_BN <= N;
+    const bool interior = !CHECK || (m0 + GD_BM <= M && n0 + GD_BN <= N);
 
     uint32_t ra[A_UNITS][FI::UNIT_DW], rb[B_UNITS][FI::UNIT_DW];
     constexpr int A_UPR = GD_BK / U;    // A units per row of the tile
@@ -125,7 +126,7 @@ k_gemm_f64(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     // edge tiles and the last K step load with bounds: elements outside the
     // matrix read as +0, and no byte past a row's last element is read
     auto load_tiles = [&](int k0) {
-        const bool edge = !interior || k0 + GD_BK > K;
+        const bool edge = CHECK && (!interior || k0 + GD_BK > K);
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
             int row, uc;
@@ -241,8 +242,15 @@ fb_status launch_f64(int kout, unsigned blocks, const void* A, int64_t lda, cons
     auto a = static_cast<const uint8_t*>(A);
     auto b = static_cast<const uint8_t*>(B);
     auto c = static_cast<uint8_t*>(C);
-#define FLYTE_F64_LAUNCH(KO, MO) \
-    k_gemm_f64<KIN, KO, MO><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K, bandA, bandB)
+    // shapes that are tile multiples take the instance without bounds checks
+    const bool check = M % GD_BM != 0 || N % GD_BN != 0 || K % GD_BK != 0;
+#define FLYTE_F64_LAUNCH(KO, MO)                                                                                   \
+    if (check)                                                                                                   \
+        k_gemm_f64<KIN, KO, MO, true><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K, bandA,  \
+                                                                        bandB);                                   \
+    else                                                                                                         \
+        k_gemm_f64<KIN, KO, MO, false><<<blocks, GD_THREADS, 0, stream>>>(a, lda, b, ldb, c, ldc, M, N, K, bandA, \
+                                                                         bandB)
     switch (kout) {
         case 2: FLYTE_F64_LAUNCH(2, MODE); break;
         case 3: FLYTE_F64_LAUNCH(3, MODE); break;

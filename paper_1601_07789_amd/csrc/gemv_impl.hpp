@@ -268,9 +268,13 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
     X(30, 64, 8, 1, 4, true, true)          \
     X(31, 32, 2, 2, 1, true, false)         \
     X(32, 16, 2, 2, 1, true, false)         \
-    X(33, 8, 2, 1, 1, true, false)
+    X(33, 8, 2, 1, 1, true, false)          \
+    X(34, 64, 1, 2, 4, true, false)         \
+    X(35, 64, 1, 4, 4, true, false)         \
+    X(36, 64, 2, 2, 4, true, false)         \
+    X(37, 64, 1, 1, 4, true, true)
 
-constexpr int kGemvNumTiles = 34;
+constexpr int kGemvNumTiles = 38;
 
 struct TileInfo {
     int lpr, rpw, u, ks, nt, staged, rows_per_block;
