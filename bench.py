@@ -518,6 +518,15 @@ def bench_blas1(flyte, workloads, torch, dev, stream):
         del x
     del nat32, back32
     torch.cuda.empty_cache()
+    # the in-tree read+write ceiling: pack to {64,8} cuts no bits (the identity
+    # codec), so it is a plain read+write dword stream with the same chunked grid
+    # and 16-byte lane units as the codec and BLAS-1 kernels
+    ceil = res["pack"][8]["GBps"]
+    out["stream_ceiling"] = {"kernel": "k_pack {64,8} (identity: a plain 16-byte-unit read+write stream, same grid)",
+                             "GBps": ceil, "frac_hbm": round(ceil / HBM_PEAK_GBPS, 4)}
+    for op in ("pack", "unpack", "axpy", "scale"):
+        for key, v in res[op].items():
+            v["frac_of_stream_ceiling"] = round(v["GBps"] / ceil, 4)
     out.update(res)
     return out
 

@@ -124,33 +124,68 @@ constexpr int kBlock = 256;
 constexpr int kUnroll = 4;
 
 // ---------------------------------------------------------------- pack
-template <class F, int MODE, int U>
+// A lane unit is NE elements (a whole number of dword groups): NE * W bytes
+// read, NE * k written.
+template <class F, int MODE, int U, int NE>
 __global__ void __launch_bounds__(kBlock)
 k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nunits, int64_t n)
 {
     using T = typename F::bits_t;
-    constexpr int D = F::UNIT_DW;
+    static_assert(NE % F::G == 0, "unit must be whole dword groups");
+    constexpr int D = NE * F::k / 4;          // packed dwords per lane unit
+    constexpr int NW = NE * F::W / 4;         // native dwords per lane unit
     constexpr bool STG = D == 5 || D == 7;   // two-instruction packed units: written as wave spans
-    __shared__ __attribute__((aligned(16))) uint32_t slices[STG ? kBlock / 64 : 1][STG ? 64 * D : 4];
+    // 32-byte input units (4 binary64 values) would take two load instructions
+    // whose spans interleave by lane; when all 64 units of a wave are in range
+    // the wave reads its 2 KiB as two lane-contiguous non-temporal KiB and hands
+    // each lane its unit through the wave's LDS slice
+    constexpr bool ISTG = NW == 8;
+    constexpr int SLICE = (ISTG ? 64 * NW : 4) > (STG ? 64 * D : 4) ? (ISTG ? 64 * NW : 4) : (STG ? 64 * D : 4);
+    __shared__ __attribute__((aligned(16))) uint32_t slices[(STG || ISTG) ? kBlock / 64 : 1][SLICE];
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
     constexpr int64_t chunk = (int64_t)kBlock * U;   // units per workgroup chunk
     for (int64_t g0 = (int64_t)blockIdx.x * chunk + threadIdx.x; g0 < nunits; g0 += (int64_t)gridDim.x * chunk) {
-        uint32_t w[U][F::UNIT_NW];
+        uint32_t w[U][NW];
+        u32x4 wc[ISTG ? U : 1][2];
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * kBlock;
-            if (g < nunits) load_stream(src + g * F::UNIT_NW, w[u]);
+            if constexpr (ISTG) {
+                const int64_t gw = g - lane;   // the wave's first unit (lanes hold consecutive units)
+                if (gw + 63 < nunits) {        // wave-uniform: every lane in range and active
+                    const u32x4* base = reinterpret_cast<const u32x4*>(src + gw * NW);
+                    wc[u][0] = __builtin_nontemporal_load(base + lane);
+                    wc[u][1] = __builtin_nontemporal_load(base + 64 + lane);
+                    return;
+                }
+            }
+            if (g < nunits) load_stream(src + g * NW, w[u]);
         });
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + u * kBlock;
+            if constexpr (ISTG) {
+                if (g - lane + 63 < nunits) {
+                    uint32_t* sl = slices[wave];
+                    *reinterpret_cast<u32x4*>(sl + 4 * lane) = wc[u][0];
+                    *reinterpret_cast<u32x4*>(sl + 256 + 4 * lane) = wc[u][1];
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    const u32x4 a0 = *reinterpret_cast<const u32x4*>(sl + 8 * lane);
+                    const u32x4 a1 = *reinterpret_cast<const u32x4*>(sl + 8 * lane + 4);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    w[u][0] = a0.x; w[u][1] = a0.y; w[u][2] = a0.z; w[u][3] = a0.w;
+                    w[u][4] = a1.x; w[u][5] = a1.y; w[u][6] = a1.z; w[u][7] = a1.w;
+                }
+            }
             if (g < nunits) {
-                T b[F::UNIT];
-                words_to_bits<F, F::UNIT>(w[u], b);
+                T b[NE];
+                words_to_bits<F, NE>(w[u], b);
 #pragma unroll
-                for (int e = 0; e < F::UNIT; ++e) b[e] = round_pack<F, MODE>(b[e]);
+                for (int e = 0; e < NE; ++e) b[e] = round_pack<F, MODE>(b[e]);
                 uint32_t P[D];
-                assemble_elems<F, F::UNIT>(b, P);
+                assemble_elems<F, NE>(b, P);
                 if constexpr (STG) {
                     if (g - lane + 63 < nunits) {   // wave-uniform: every lane in range and active
                         span_store<D>(dst + (g - lane) * D, slices[wave], lane, P);
@@ -162,8 +197,8 @@ k_pack(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst, int64_t nun
         });
     }
     if (blockIdx.x == 0) {
-        const int64_t i = nunits * F::UNIT + threadIdx.x;
-        if (threadIdx.x < F::UNIT && i < n) {
+        const int64_t i = nunits * NE + threadIdx.x;
+        if (threadIdx.x < NE && i < n) {
             T u;
             if constexpr (F::W == 4) u = src[i];
             else u = (uint64_t(src[2 * i + 1]) << 32) | src[2 * i];
@@ -575,9 +610,14 @@ extern "C" fb_status fb_pack(fb_format f, const void* src_native, void* dst_pack
     if (st != FB_OK || n == 0) return st;
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
-        const int64_t nunits = (int64_t)(n / F::UNIT);
+        // pack reads W/k times what it writes, so its lane unit is sized by the
+        // input where whole dword groups allow it: 16 bytes (2 binary64 or 4
+        // binary32 values, one lane-contiguous load per wave instruction),
+        // else the format's own unit
+        constexpr int NE = (F::base == 64 && F::G <= 2) ? 2 : (F::base == 32 && F::G <= 4) ? 4 : F::UNIT;
+        const int64_t nunits = (int64_t)(n / NE);
         return dispatch_round(f, [&](auto rt) {
-            k_pack<F, decltype(rt)::value, kUnroll><<<chunk_grid(nunits, kUnroll), kBlock, 0, stream>>>(
+            k_pack<F, decltype(rt)::value, kUnroll, NE><<<chunk_grid(nunits, kUnroll), kBlock, 0, stream>>>(
                 static_cast<const uint32_t*>(src_native), static_cast<uint32_t*>(dst_packed), nunits, (int64_t)n);
             return check_launch("fb_pack");
         });
@@ -591,9 +631,11 @@ extern "C" fb_status fb_unpack(fb_format f, const void* src_packed, void* dst_na
     return dispatch_format(f, [&](auto tag) {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         // unpack writes W/k times what it reads, so its lane unit is sized by the
-        // output: 16 bytes (2 binary64 or 4 binary32 values) where whole dwords
-        // of input allow it, else 4 elements (odd k with binary64)
-        constexpr int NE = (F::base == 64) ? ((F::k % 2 == 0) ? 2 : 4) : 4;
+        // output: 16 bytes (2 binary64 or 4 binary32 values) for binary64 k = 6, 8
+        // and binary32, else 4 binary64 values (32 bytes, stored through the
+        // wave's LDS slice as two lane-contiguous KiB), which also gives k = 2, 4
+        // loads of 8 and 16 bytes instead of 4 and 8
+        constexpr int NE = (F::base == 64) ? ((F::k == 6 || F::k == 8) ? 2 : 4) : 4;
         static_assert(NE % F::G == 0, "unit must be whole dword groups");
         const int64_t nunits = (int64_t)(n / NE);
         k_unpack<F, kUnroll, NE><<<chunk_grid(nunits, kUnroll), kBlock, 0, stream>>>(
