@@ -6,18 +6,19 @@
 //
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
-// wave tiles keep LDS operand traffic below the LDS bandwidth (a 64 x 128 wave
-// tile reads about 94 B/clk of LDS per CU at the MFMA peak, against 128
-// available).  8 waves per workgroup, two per SIMD, in 256 x 256 x 64 tiles
-// as 4 x 2 waves of 64 x 128 (144 KiB of LDS); shapes that are not multiples
-// of 256 use 128 x 128 x 64.  K is walked in BK steps through double-buffered
-// LDS (one barrier per step; the next step's global loads are issued before
-// the current step's MFMAs; the last step is peeled).  LDS rows are padded by
-// 16 bytes, so the 16-byte operand reads of 16 lanes hit distinct banks.  B is
-// stored in LDS n-major (k contiguous): each thread loads KR rows of B and
-// transposes them in registers with v_perm_b32.  Every MFMA operand is one
-// ds_read_b128.  Workgroups are renumbered so that consecutive tiles of C run
-// on the same XCD (sharing its L2), grouped 8 tile-rows at a time.
+// wave tiles keep LDS operand traffic low.  8 waves per workgroup, two per
+// SIMD, in 256 x 256 x 64 tiles as 4 x 2 waves of 64 x 128 (144 KiB of LDS);
+// shapes that are not multiples of 256 use 128 x 128 x 64.  K is walked in BK
+// steps through double-buffered LDS (one barrier per step; the next step's
+// global loads are issued before the current step's MFMAs; the last step is
+// peeled).  A is stored m-major (k contiguous, rows padded by 16 bytes, so
+// the 16-byte operand reads of 16 lanes hit distinct banks) and read with
+// ds_read_b128.  B is stored as it is in memory, k-major (n contiguous, rows
+// padded by 64 bytes), from 16-byte global loads, and each operand fragment
+// is read with two transposing LDS reads (ds_read_b64_tr_b16: the 16 lanes of
+// a group address a 4 x 16 block, 4 k-rows of 16 columns, and lane i receives
+// column i's 4 k-values).  Workgroups are renumbered so that consecutive tiles
+// of C run on the same XCD (sharing its L2), grouped 8 tile-rows at a time.
 #include "codec.hpp"
 #include "common.hpp"
 
@@ -26,6 +27,9 @@ namespace flyte {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef short i16x4_t __attribute__((ext_vector_type(4)));
+typedef short i16x8_t __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) i16x4_t lds_i16x4_t;
 
 // Tile index of this workgroup: XCD-aware renumbering, then 8-row groups.
 __device__ __forceinline__ void gemm_tile_coords(int ntm, int ntn, int& tm, int& tn)
@@ -43,47 +47,32 @@ __device__ __forceinline__ void gemm_tile_coords(int ntm, int ntn, int& tm, int&
 }
 
 // Tile configuration: BM x BN x BK workgroup tile, WGM x WGN waves (wave tile
-// (BM/WGM) x (BN/WGN) as 16 x 16 MFMA tiles), B loaded in groups of KR rows.
-// Stores KR bf16 (KR/2 dwords) at an LDS address: one ds_write_b128 or b64.
-template <int KR>
-__device__ __forceinline__ void store_row_chunk(uint16_t* dst, const uint32_t (&v)[KR / 2])
-{
-    if constexpr (KR == 8) {
-        *reinterpret_cast<u32x4_t*>(dst) = u32x4_t{v[0], v[1], v[2], v[3]};
-    } else {
-        typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
-        *reinterpret_cast<u32x2_t*>(dst) = u32x2_t{v[0], v[1]};
-    }
-}
-
-template <int BM, int BN, int BK, int WGM, int WGN, int KR>
+// (BM/WGM) x (BN/WGN) as 16 x 16 MFMA tiles).
+template <int BM, int BN, int BK, int WGM, int WGN>
 struct B32Tile {
     static constexpr int THREADS = 64 * WGM * WGN;
     static constexpr int TM = BM / WGM, TN = BN / WGN;
     static constexpr int FM = TM / 16, FN = TN / 16;
-    static constexpr int ROW = BK + 8;                  // bf16 per padded LDS row
-    static constexpr int A_TILE = BM * ROW, B_TILE = BN * ROW;
+    static constexpr int ROW = BK + 8;                  // bf16 per padded LDS row of A
+    static constexpr int BROW = BN + 32;                // bf16 per padded LDS row of B (k-major)
+    static constexpr int A_TILE = BM * ROW, B_TILE = BK * BROW;
     static constexpr int STAGE = A_TILE + B_TILE;
-    // A: chunks of 8 consecutive bf16 of a row (16 bytes)
-    static constexpr int CPR = BK / 8;
-    static constexpr int A_N = BM * CPR / THREADS;
-    // B: groups of KR k-rows x 2 columns (one dword per row)
-    static constexpr int B_GPR = BN / 2;
-    static constexpr int B_G = (BK / KR) * B_GPR / THREADS;
+    // A: chunks of 8 consecutive bf16 of a row (16 bytes); B: the same along n
+    static constexpr int CPR = BK / 8, A_N = BM * CPR / THREADS;
+    static constexpr int BCPR = BN / 8, B_N = BK * BCPR / THREADS;
     static_assert(BK % 32 == 0 && TM % 16 == 0 && TN % 16 == 0, "tile shape");
     static_assert(A_N * THREADS == BM * CPR && A_N >= 1, "A staging must divide evenly");
-    static_assert(B_G * THREADS == (BK / KR) * B_GPR && B_G >= 1, "B staging must divide evenly");
-    static_assert(KR == 4 || KR == 8, "B group rows");
+    static_assert(B_N * THREADS == BK * BCPR && B_N >= 1, "B staging must divide evenly");
 };
 
-template <int BM, int BN, int BK, int WGM, int WGN, int KR>
+template <int BM, int BN, int BK, int WGM, int WGN>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            float* __restrict__ C, int64_t ldc, int M, int N, int K)
 {
     // A and B are the packed {32,2} matrices (bfloat16 patterns).
-    using T = B32Tile<BM, BN, BK, WGM, WGN, KR>;
-    constexpr int THREADS = T::THREADS, ROW = T::ROW;
+    using T = B32Tile<BM, BN, BK, WGM, WGN>;
+    constexpr int THREADS = T::THREADS, ROW = T::ROW, BROW = T::BROW;
     constexpr int FM = T::FM, FN = T::FN;
     // [stage][A, B]
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][T::STAGE];
@@ -95,8 +84,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
     const int wm = wid / WGN, wn = wid % WGN;
 
-    uint32_t ra[T::A_N][4];
-    uint32_t rb[T::B_G][KR];
+    u32x4_t ra[T::A_N], rb[T::B_N];
 
     auto a_tile = [&](int s) { return lds[s]; };
     auto b_tile = [&](int s) { return lds[s] + T::A_TILE; };
@@ -105,14 +93,12 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
 #pragma unroll
         for (int i = 0; i < T::A_N; ++i) {
             const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
-            load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * 8) * 2), ra[i]);
+            ra[i] = *reinterpret_cast<const u32x4_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * 8) * 2);
         }
 #pragma unroll
-        for (int g = 0; g < T::B_G; ++g) {
-            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
-#pragma unroll
-            for (int r = 0; r < KR; ++r)
-                rb[g][r] = *reinterpret_cast<const uint32_t*>(B + ((int64_t)(k0 + kg * KR + r) * ldb + n0 + 2 * np) * 2);
+        for (int i = 0; i < T::B_N; ++i) {
+            const int c = t + THREADS * i, row = c / T::BCPR, nc = c % T::BCPR;
+            rb[i] = *reinterpret_cast<const u32x4_t*>(B + ((int64_t)(k0 + row) * ldb + n0 + nc * 8) * 2);
         }
     };
 
@@ -120,21 +106,12 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
 #pragma unroll
         for (int i = 0; i < T::A_N; ++i) {
             const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
-            *reinterpret_cast<u32x4_t*>(a_tile(s) + row * ROW + kc * 8) = u32x4_t{ra[i][0], ra[i][1], ra[i][2], ra[i][3]};
+            *reinterpret_cast<u32x4_t*>(a_tile(s) + row * ROW + kc * 8) = ra[i];
         }
-        uint16_t* Bh = b_tile(s);
 #pragma unroll
-        for (int g = 0; g < T::B_G; ++g) {
-            const int gi = t + THREADS * g, np = gi % T::B_GPR, kg = gi / T::B_GPR;
-            // row r holds columns (2np, 2np+1) as low/high halves: transpose to k-contiguous columns
-            uint32_t c0[KR / 2], c1[KR / 2];
-#pragma unroll
-            for (int i = 0; i < KR / 2; ++i) {
-                c0[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1], rb[g][2 * i], 0x05040100u);
-                c1[i] = __builtin_amdgcn_perm(rb[g][2 * i + 1], rb[g][2 * i], 0x07060302u);
-            }
-            store_row_chunk<KR>(Bh + (2 * np) * ROW + kg * KR, c0);
-            store_row_chunk<KR>(Bh + (2 * np + 1) * ROW + kg * KR, c1);
+        for (int i = 0; i < T::B_N; ++i) {
+            const int c = t + THREADS * i, row = c / T::BCPR, nc = c % T::BCPR;
+            *reinterpret_cast<u32x4_t*>(b_tile(s) + row * BROW + nc * 8) = rb[i];
         }
     };
 
@@ -161,8 +138,14 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         auto read_a = [&](int ks, int i) {
             return *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
         };
+        // transposing read: lane s of a 16-lane group addresses k-row 8 (lane / 16) + s / 4 (+ 4 for
+        // the upper half) and columns 4 (s % 4) .. + 3 of the fragment's 16 columns
+        const uint16_t* Bl = Bh + (8 * (lane / 16) + r16 / 4) * BROW + wn * T::TN + 4 * (r16 % 4);
         auto read_b = [&](int ks, int j) {
-            return *reinterpret_cast<const bf16x8_t*>(Bh + (wn * T::TN + j * 16 + r16) * ROW + ks * 32 + kq);
+            const uint16_t* p = Bl + ks * 32 * BROW + j * 16;
+            const i16x4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4_t*)(p));
+            const i16x4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4_t*)(p + 4 * BROW));
+            return __builtin_bit_cast(bf16x8_t, i16x8_t(__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7)));
         };
         bf16x8_t a[2][FM], b[FN];
         __builtin_amdgcn_s_setprio(1);
@@ -184,14 +167,14 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks & 1][i], b[j], acc[i][j], 0, 0, 0);
             }
         }
-        __builtin_amdgcn_sched_group_barrier(0x100, FM + 1, 0);   // LDS reads
+        __builtin_amdgcn_sched_group_barrier(0x100, FM + 2, 0);   // LDS reads
 #pragma unroll
         for (int ks = 0; ks < KSN; ++ks) {
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
                 if (ks < KSN - 1 || j < FN - 1) {
-                    if (j == JA && ks + 1 < KSN) __builtin_amdgcn_sched_group_barrier(0x100, 1 + FM, 0);
-                    else __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    if (j == JA && ks + 1 < KSN) __builtin_amdgcn_sched_group_barrier(0x100, 2 + FM, 0);
+                    else __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
                 }
                 __builtin_amdgcn_sched_group_barrier(0x008, FM, 0);   // MFMAs
             }
@@ -229,12 +212,12 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
             }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, int KR>
+template <int BM, int BN, int BK, int WGM, int WGN>
 static void launch_b32(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                        int64_t ldc, hipStream_t stream)
 {
     const unsigned blocks = (unsigned)((M / BM) * (N / BN));
-    k_gemm_b32<BM, BN, BK, WGM, WGN, KR><<<blocks, 64 * WGM * WGN, 0, stream>>>(
+    k_gemm_b32<BM, BN, BK, WGM, WGN><<<blocks, 64 * WGM * WGN, 0, stream>>>(
         static_cast<const uint8_t*>(A), lda, static_cast<const uint8_t*>(B), ldb, static_cast<float*>(C), ldc, (int)M,
         (int)N, (int)K);
 }
@@ -244,9 +227,9 @@ fb_status gemm_bf16_launch(int64_t M, int64_t N, int64_t K, const void* A, int64
                            void* C, int64_t ldc, hipStream_t stream)
 {
     if (M % 256 == 0 && N % 256 == 0)
-        launch_b32<256, 256, 64, 4, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        launch_b32<256, 256, 64, 4, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     else
-        launch_b32<128, 128, 64, 2, 2, 8>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        launch_b32<128, 128, 64, 2, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     return check_launch("fb_gemm");
 }
 
