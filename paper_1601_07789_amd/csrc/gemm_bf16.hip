@@ -7,17 +7,20 @@
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
 // wave tiles keep LDS operand traffic low.  8 waves per workgroup, two per
-// SIMD, in 256 x 256 x 64 tiles as 4 x 2 waves of 64 x 128 (144 KiB of LDS);
+// SIMD, in 256 x 256 x 64 tiles as 4 x 2 waves of 64 x 128 (136 KiB of LDS);
 // shapes that are not multiples of 256 use 128 x 128 x 64.  K is walked in BK
 // steps through double-buffered LDS (one barrier per step; the next step's
 // global loads are issued before the current step's MFMAs; the last step is
 // peeled).  A is stored m-major (k contiguous, rows padded by 16 bytes, so
 // the 16-byte operand reads of 16 lanes hit distinct banks) and read with
-// ds_read_b128.  B is stored as it is in memory, k-major (n contiguous, rows
-// padded by 64 bytes), from 16-byte global loads, and each operand fragment
-// is read with two transposing LDS reads (ds_read_b64_tr_b16: the 16 lanes of
-// a group address a 4 x 16 block, 4 k-rows of 16 columns, and lane i receives
-// column i's 4 k-values).  Workgroups are renumbered so that consecutive tiles
+// ds_read_b128.  B is stored as it is in memory, k-major (n contiguous), from
+// 16-byte global loads, and each operand fragment is read with two
+// transposing LDS reads (ds_read_b64_tr_b16: the 16 lanes of a group address
+// a 4 x 16 block, 4 k-rows of 16 columns, and lane i receives column i's 4
+// k-values).  A 32-lane read phase covers k-rows r..r+3 and r+8..r+11; B
+// rows are unpadded and 16-byte chunk c of k-row R sits at c ^ 2 g(R), with
+// g(R) = (R & 3) | ((R >> 1) & 4), so those 8 rows' 32-byte pieces fall in 8
+// distinct 32-byte bank groups.  Workgroups are renumbered so that consecutive tiles
 // of C run on the same XCD (sharing its L2), grouped 8 tile-rows at a time.
 #include "codec.hpp"
 #include "common.hpp"
@@ -54,7 +57,7 @@ struct B32Tile {
     static constexpr int TM = BM / WGM, TN = BN / WGN;
     static constexpr int FM = TM / 16, FN = TN / 16;
     static constexpr int ROW = BK + 8;                  // bf16 per padded LDS row of A
-    static constexpr int BROW = BN + 32;                // bf16 per padded LDS row of B (k-major)
+    static constexpr int BROW = BN;                     // bf16 per LDS row of B (k-major, swizzled)
     static constexpr int A_TILE = BM * ROW, B_TILE = BK * BROW;
     static constexpr int STAGE = A_TILE + B_TILE;
     // A: chunks of 8 consecutive bf16 of a row (16 bytes); B: the same along n
@@ -63,6 +66,7 @@ struct B32Tile {
     static_assert(BK % 32 == 0 && TM % 16 == 0 && TN % 16 == 0, "tile shape");
     static_assert(A_N * THREADS == BM * CPR && A_N >= 1, "A staging must divide evenly");
     static_assert(B_N * THREADS == BK * BCPR && B_N >= 1, "B staging must divide evenly");
+    static_assert(BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
 };
 
 template <int BM, int BN, int BK, int WGM, int WGN>
@@ -111,7 +115,8 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
 #pragma unroll
         for (int i = 0; i < T::B_N; ++i) {
             const int c = t + THREADS * i, row = c / T::BCPR, nc = c % T::BCPR;
-            *reinterpret_cast<u32x4_t*>(b_tile(s) + row * BROW + nc * 8) = rb[i];
+            const int g = (row & 3) | ((row >> 1) & 4);
+            *reinterpret_cast<u32x4_t*>(b_tile(s) + row * BROW + (nc ^ (2 * g)) * 8) = rb[i];
         }
     };
 
@@ -139,10 +144,12 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
             return *reinterpret_cast<const bf16x8_t*>(Ah + (wm * T::TM + i * 16 + r16) * ROW + ks * 32 + kq);
         };
         // transposing read: lane s of a 16-lane group addresses k-row 8 (lane / 16) + s / 4 (+ 4 for
-        // the upper half) and columns 4 (s % 4) .. + 3 of the fragment's 16 columns
-        const uint16_t* Bl = Bh + (8 * (lane / 16) + r16 / 4) * BROW + wn * T::TN + 4 * (r16 % 4);
+        // the upper half) and columns 4 (s % 4) .. + 3 of the fragment's 16 columns, whose block of
+        // 16 columns sits at block index ^ g(row) (g of those rows is the same for every ks and half)
+        const uint16_t* Bl = Bh + (8 * (lane / 16) + r16 / 4) * BROW + 4 * (r16 % 4);
+        const int bg = (r16 / 4) | (((lane / 16) & 1) << 2);
         auto read_b = [&](int ks, int j) {
-            const uint16_t* p = Bl + ks * 32 * BROW + j * 16;
+            const uint16_t* p = Bl + ks * 32 * BROW + ((wn * FN + j) ^ bg) * 16;
             const i16x4_t lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4_t*)(p));
             const i16x4_t hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4_t*)(p + 4 * BROW));
             return __builtin_bit_cast(bf16x8_t, i16x8_t(__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7)));

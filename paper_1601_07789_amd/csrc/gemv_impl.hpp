@@ -272,9 +272,11 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
     X(34, 64, 1, 2, 4, true, false)         \
     X(35, 64, 1, 4, 4, true, false)         \
     X(36, 64, 2, 2, 4, true, false)         \
-    X(37, 64, 1, 1, 4, true, true)
+    X(37, 64, 1, 1, 4, true, true)          \
+    X(38, 64, 8, 2, 4, true, false)         \
+    X(39, 64, 4, 2, 2, true, false)
 
-constexpr int kGemvNumTiles = 38;
+constexpr int kGemvNumTiles = 40;
 
 struct TileInfo {
     int lpr, rpw, u, ks, nt, staged, rows_per_block;
