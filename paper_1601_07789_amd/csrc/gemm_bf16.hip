@@ -1,8 +1,8 @@
 // GEMM on {32,2} operands with BF16 matrix cores (gfx950): the stored 2-byte
 // patterns are bfloat16 operands as they are (the 16-bit flyte of Table 1 is
 // bit-for-bit bfloat16).  C = A B, A M x K and B K x N row-major packed, C
-// FP32 row-major, M and N multiples of 128 and K of 64 (other shapes and the
-// split products of {32,3} run on the bfloat16-piece GEMM).
+// FP32 row-major, any M, N, K (the split products of {32,3} run on the
+// bfloat16-piece GEMM).
 //
 // Tiling: a workgroup computes a BM x BN tile of C with WGM x WGN waves, each
 // wave a (BM/WGM) x (BN/WGN) tile of v_mfma_f32_16x16x32_bf16 results.  Large
@@ -22,6 +22,15 @@
 // g(R) = (R & 3) | ((R >> 1) & 4), so those 8 rows' 32-byte pieces fall in 8
 // distinct 32-byte bank groups.  Workgroups are renumbered so that consecutive tiles
 // of C run on the same XCD (sharing its L2), grouped 8 tile-rows at a time.
+//
+// Shapes that are not tile multiples run the EDGE instances, whose K loop has
+// the same loads as the full-tile instance: a thread's rows of A past M read
+// row M - 1 and its 8-column chunks of B past N read the last chunk (those
+// results are not stored; the clamps are fixed per thread).  A last, partial
+// K step is peeled after the loop and loads elements (positions past K read
+// as zero, so nothing past a row's end is read).  When N is not a multiple of
+// 8 (EDGE = 2), the chunk of B that N cuts is read element by element in every
+// step.  Only the entries inside M x N are stored.
 #include "codec.hpp"
 #include "common.hpp"
 
@@ -69,7 +78,22 @@ struct B32Tile {
     static_assert(BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
 };
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+__device__ __forceinline__ int pc_clamp8(int v) { return v < 0 ? 0 : (v > 8 ? 8 : v); }
+
+// 8 bfloat16 from p, element e read only when e < nvalid (else zero; nvalid may be <= 0).
+__device__ __forceinline__ u32x4_t load8_edge(const uint8_t* p, int nvalid)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const uint32_t lo = (2 * d < nvalid) ? *reinterpret_cast<const uint16_t*>(p + 4 * d) : 0u;
+        const uint32_t hi = (2 * d + 1 < nvalid) ? *reinterpret_cast<const uint16_t*>(p + 4 * d + 2) : 0u;
+        w[d] = lo | (hi << 16);
+    }
+    return u32x4_t{w[0], w[1], w[2], w[3]};
+}
+
+template <int BM, int BN, int BK, int WGM, int WGN, int EDGE>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
            float* __restrict__ C, int64_t ldc, int M, int N, int K)
@@ -81,7 +105,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     // [stage][A, B]
     __shared__ __attribute__((aligned(16))) uint16_t lds[2][T::STAGE];
 
-    const int ntm = M / BM, ntn = N / BN;
+    const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
     int tm, tn;
     gemm_tile_coords(ntm, ntn, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
@@ -93,16 +117,47 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
     auto a_tile = [&](int s) { return lds[s]; };
     auto b_tile = [&](int s) { return lds[s] + T::A_TILE; };
 
+    // a thread's rows of A and 8-column chunks of B, clamped into the matrix (EDGE)
+    auto a_row = [&](int i) {
+        const int row = m0 + (t + THREADS * i) / T::CPR;
+        return (int64_t)(EDGE && row >= M ? M - 1 : row);
+    };
+    auto b_col = [&](int i) {
+        const int col = n0 + ((t + THREADS * i) % T::BCPR) * 8;
+        return (int64_t)(EDGE == 1 && col >= N ? N - 8 : col);
+    };
+    // elements of B's chunk i inside the matrix (EDGE = 2: N cuts a chunk), 0..8
+    auto b_valid = [&](int i) { return pc_clamp8(N - (n0 + ((t + THREADS * i) % T::BCPR) * 8)); };
+
+    // a full K step at k0
     auto load_tiles = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < T::A_N; ++i) {
-            const int c = t + THREADS * i, row = c / T::CPR, kc = c % T::CPR;
-            ra[i] = *reinterpret_cast<const u32x4_t*>(A + ((int64_t)(m0 + row) * lda + k0 + kc * 8) * 2);
+            const int kc = (t + THREADS * i) % T::CPR;
+            ra[i] = *reinterpret_cast<const u32x4_t*>(A + (a_row(i) * lda + k0 + kc * 8) * 2);
         }
 #pragma unroll
         for (int i = 0; i < T::B_N; ++i) {
-            const int c = t + THREADS * i, row = c / T::BCPR, nc = c % T::BCPR;
-            rb[i] = *reinterpret_cast<const u32x4_t*>(B + ((int64_t)(k0 + row) * ldb + n0 + nc * 8) * 2);
+            const int row = (t + THREADS * i) / T::BCPR;
+            const uint8_t* p = B + ((int64_t)(k0 + row) * ldb + b_col(i)) * 2;
+            if (EDGE == 2 && b_valid(i) < 8) rb[i] = load8_edge(p, b_valid(i));
+            else rb[i] = *reinterpret_cast<const u32x4_t*>(p);
+        }
+    };
+    // the last, partial K step at k0: positions past K read as zero
+    auto load_tail = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < T::A_N; ++i) {
+            const int kk = k0 + ((t + THREADS * i) % T::CPR) * 8;
+            ra[i] = load8_edge(A + (a_row(i) * lda + kk) * 2, K - kk);
+        }
+#pragma unroll
+        for (int i = 0; i < T::B_N; ++i) {
+            const int kr = k0 + (t + THREADS * i) / T::BCPR;
+            const uint8_t* p = B + ((int64_t)(kr < K ? kr : K - 1) * ldb + b_col(i)) * 2;
+            if (kr >= K) rb[i] = u32x4_t{0u, 0u, 0u, 0u};
+            else if (EDGE == 2) rb[i] = load8_edge(p, b_valid(i));
+            else rb[i] = *reinterpret_cast<const u32x4_t*>(p);
         }
     };
 
@@ -189,17 +244,26 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         __builtin_amdgcn_s_setprio(0);
     };
 
-    // the last K step is peeled so the loop body has no branches
-    const int KT = K / BK;
-    load_tiles(0);
+    // the last K step is peeled so the loop body has no branches; a partial
+    // last step (EDGE instances) is loaded after the loop
+    const int KF = K / BK, KT = EDGE ? (K + BK - 1) / BK : KF;
+    if (!EDGE || KF > 0) load_tiles(0);
+    else load_tail(0);
     store_tiles(0);
     __syncthreads();
-    for (int kt = 0; kt < KT - 1; ++kt) {
+    for (int kt = 0; kt < KF - 1; ++kt) {
         const int s = kt & 1;
         load_tiles((kt + 1) * BK);
         // keep the next step's global loads ahead of this step's MFMAs, so
         // their latency is covered by the whole step
         __builtin_amdgcn_sched_barrier(0);
+        compute(s);
+        store_tiles(s ^ 1);
+        __syncthreads();
+    }
+    if (EDGE && KT > KF && KF > 0) {
+        const int s = (KF - 1) & 1;
+        load_tail(KF * BK);
         compute(s);
         store_tiles(s ^ 1);
         __syncthreads();
@@ -215,28 +279,43 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
             for (int r = 0; r < 4; ++r) {
                 const int row = m0 + wm * T::TM + i * 16 + 4 * (lane / 16) + r;
                 const int col = n0 + wn * T::TN + j * 16 + lane % 16;
-                C[(int64_t)row * ldc + col] = acc[i][j][r];
+                if (!EDGE || (row < M && col < N)) C[(int64_t)row * ldc + col] = acc[i][j][r];
             }
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN>
+template <int BM, int BN, int BK, int WGM, int WGN, int EDGE>
 static void launch_b32(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                        int64_t ldc, hipStream_t stream)
 {
-    const unsigned blocks = (unsigned)((M / BM) * (N / BN));
-    k_gemm_b32<BM, BN, BK, WGM, WGN><<<blocks, 64 * WGM * WGN, 0, stream>>>(
+    const unsigned blocks = (unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
+    k_gemm_b32<BM, BN, BK, WGM, WGN, EDGE><<<blocks, 64 * WGM * WGN, 0, stream>>>(
         static_cast<const uint8_t*>(A), lda, static_cast<const uint8_t*>(B), ldb, static_cast<float*>(C), ldc, (int)M,
         (int)N, (int)K);
 }
 
-// {32,2} operands, M and N multiples of 128, K of 64 (checked by the caller).
+template <int BM, int BN, int WGM, int WGN>
+static void launch_b32_shape(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
+                             void* C, int64_t ldc, hipStream_t stream)
+{
+    if (M % BM == 0 && N % BN == 0 && K % 64 == 0)
+        launch_b32<BM, BN, 64, WGM, WGN, 0>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    else if (N % 8 == 0)
+        launch_b32<BM, BN, 64, WGM, WGN, 1>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    else
+        launch_b32<BM, BN, 64, WGM, WGN, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+}
+
+// {32,2} operands, any M, N >= 1 and K >= 1 (checked by the caller): 256 x 256
+// tiles when the full-tile instance applies or when those tiles still give
+// every compute unit one, else 128 x 128.
 fb_status gemm_bf16_launch(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B, int64_t ldb,
                            void* C, int64_t ldc, hipStream_t stream)
 {
-    if (M % 256 == 0 && N % 256 == 0)
-        launch_b32<256, 256, 64, 4, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    const bool full256 = M % 256 == 0 && N % 256 == 0 && K % 64 == 0;
+    if (full256 || ((M + 255) / 256) * ((N + 255) / 256) >= device_cu_count())
+        launch_b32_shape<256, 256, 4, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     else
-        launch_b32<128, 128, 64, 2, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+        launch_b32_shape<128, 128, 2, 2>(M, N, K, A, lda, B, ldb, C, ldc, stream);
     return check_launch("fb_gemm");
 }
 

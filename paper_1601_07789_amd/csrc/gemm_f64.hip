@@ -1,6 +1,7 @@
 // fb_gemm / fb_gemm_ex: argument checks and dispatch to the BF16 matrix-core
-// paths ({32,2}, {32,3}, and the scaled pieces of {64,2..4}) or the FP64
-// matrix-core path (binary64 formats).
+// paths ({32,2} on the bfloat16 kernel; {32,3} and the scaled pieces of
+// {64,2..4} on the piece kernel) or the FP64 matrix-core path (binary64
+// formats).
 #include "gemm_f64_impl.hpp"
 #include "gemm_pieces.hpp"
 
@@ -87,13 +88,8 @@ extern "C" fb_status fb_gemm_ex(fb_format fa, fb_format fb, fb_format fc, int64_
         return check_launch("fb_gemm");
     }
     const bool all = (flags & FB_GEMM_ALL_PRODUCTS) != 0;
-    if (bf16) {
-        // tile multiples take the tuned bfloat16 kernel, other shapes the bounded piece loader
-        if (M % 128 == 0 && N % 128 == 0 && K % 64 == 0)
-            return gemm_bf16_launch(M, N, K, A, lda, B, ldb, C, ldc, stream);
-        return gemm_pieces_b32(2, false, M, N, K, A, lda, B, ldb, C, ldc, stream);
-    }
-    if (three) return gemm_pieces_b32(3, all, M, N, K, A, lda, B, ldb, C, ldc, stream);
+    if (bf16) return gemm_bf16_launch(M, N, K, A, lda, B, ldb, C, ldc, stream);
+    if (three) return gemm_pieces_b32(all, M, N, K, A, lda, B, ldb, C, ldc, stream);
     if (pieces64) {
         // scaling pass (shifts and band flags in the stream workspace), the
         // piece GEMM on every tile of scalable bands, then FP64 on the rest

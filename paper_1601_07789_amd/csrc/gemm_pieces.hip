@@ -1,4 +1,4 @@
-// bfloat16-piece GEMMs: the binary32 entry ({32,2} and {32,3} operands) and
+// bfloat16-piece GEMMs: the binary32 entry ({32,3} operands) and
 // the scaling pass of the scaled binary64 operands ({64,2..4}).  The kernel
 // template and the loaders are in gemm_pieces_impl.hpp; the binary64
 // instantiations are in gemm_pieces_b64.hpp, one source file per input k.
@@ -128,11 +128,10 @@ __global__ void __launch_bounds__(128) k_pc_bands(const uint8_t* __restrict__ ro
     if (threadIdx.x == 0) band[blockIdx.x] = (uint8_t)(any != 0);
 }
 
-fb_status gemm_pieces_b32(int k, bool all_products, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+fb_status gemm_pieces_b32(bool all_products, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                           const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t stream)
 {
     const PcScale none{};
-    if (k == 2) return pc_run<PcB32K2, 1, 256, 256, 2, 4, 0, 0>(M, N, K, A, lda, B, ldb, C, ldc, none, stream);
     if (all_products) return pc_run<PcB32K3, 15, 256, 256, 2, 4, 0, 0>(M, N, K, A, lda, B, ldb, C, ldc, none, stream);
     return pc_run<PcB32K3, 7, 256, 256, 2, 4, 0, 0>(M, N, K, A, lda, B, ldb, C, ldc, none, stream);
 }

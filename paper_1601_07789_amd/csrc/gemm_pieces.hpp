@@ -23,8 +23,8 @@ struct PcScale {
 // Row slabs of the column-statistics pass.
 constexpr int kPcColSlabs = 16;
 
-// {32,2} (k = 2) or {32,3} (k = 3; all_products adds lo*lo) operands, FP32 C.
-fb_status gemm_pieces_b32(int k, bool all_products, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+// {32,3} operands (all_products adds lo*lo), FP32 C.
+fb_status gemm_pieces_b32(bool all_products, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
                           const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t stream);
 
 // Device bytes the scaling pass needs for an M x K times K x N product.

@@ -9,7 +9,6 @@
 // accumulators (Section 3.1: compute in the next type that holds the data;
 // Section 4.3: conversion is part of the load).
 //
-//  {32,2}: the stored pattern is a bfloat16 (one piece).
 //  {32,3}: hi = the top two bytes (a NaN gets the quiet bit, so it stays
 //    NaN), lo = x - hi rounded to bfloat16 (exact for biased exponent >= 9;
 //    0 for Inf/NaN).  Products hi*hi + hi*lo + lo*hi, or all four.
@@ -81,14 +80,9 @@ __device__ __forceinline__ uint32_t pc_top_pair(uint32_t a, uint32_t b)
 // K step is not finite.  shift[e] (scaled formats): (e_ref - 127) << 20 of
 // the row or column of element e.
 
-struct PcB32K2 {
-    static constexpr int KB = 2, PIECES = 1, ROUND_P = -1;
-    static constexpr bool SCALED = false, RAW = true;   // the stored pairs are the piece pairs
-};
-
 struct PcB32K3 {
     static constexpr int KB = 3, PIECES = 2, ROUND_P = 1;
-    static constexpr bool SCALED = false, RAW = false, SPECIALS = true;
+    static constexpr bool SCALED = false, SPECIALS = true;
     __device__ static void values(const uint32_t (&d)[3], const int32_t (&)[4], uint32_t (&x)[4])
     {
         unpack_elems<Fmt<32, 3>, 4>(d, x);
@@ -114,7 +108,7 @@ struct PcB32K3 {
 template <int K>
 struct PcB64 {
     static constexpr int KB = K, PIECES = K - 1, ROUND_P = -1;
-    static constexpr bool SCALED = true, RAW = false, SPECIALS = false;
+    static constexpr bool SCALED = true, SPECIALS = false;
     __device__ static void values(const uint32_t (&d)[K], const int32_t (&shift)[4], uint32_t (&x)[4])
     {
         uint64_t u[4];
@@ -307,90 +301,69 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     auto store_tiles = [&](int s) {
         uint16_t* As = lds[s];
         uint16_t* Bs = lds[s] + P * A_TILE;
-        if constexpr (LD::RAW) {
-            // bfloat16 operands: A chunks are already pairs along k; B rows are
-            // transposed pairwise into pairs along k
+        uint32_t xa[A_CH][4], xb[B_GR][4][4];   // values: A [chunk][element], B [group][k-row][column]
+#pragma unroll
+        for (int i = 0; i < A_CH; ++i) LD::values(ra[i], sa[i], xa[i]);
+#pragma unroll
+        for (int g = 0; g < B_GR; ++g)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) LD::values(rb[g][r], sb[g], xb[g][r]);
+        // piece pairs: A along its chunk, B down its 4 k-rows
+        auto a_pair = [&](auto ip, auto safe, int i, int h) {
+            return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xa[i][2 * h], xa[i][2 * h + 1]);
+        };
+        auto b_pair = [&](auto ip, auto safe, int g, int c, int h) {
+            return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][2 * h][c], xb[g][2 * h + 1][c]);
+        };
+        auto put = [&](auto safe) {
 #pragma unroll
             for (int i = 0; i < A_CH; ++i) {
                 const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
-                *reinterpret_cast<pc_u32x2*>(As + row * PC_ROW + kc * 4) = pc_u32x2{ra[i][0], ra[i][1]};
+                static_for<P>([&](auto ip) {
+                    constexpr int p = decltype(ip)::value;
+                    *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + row * PC_ROW + kc * 4) =
+                        pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
+                });
             }
 #pragma unroll
             for (int g = 0; g < B_GR; ++g) {
                 const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const uint32_t sel = (c % 2) ? 0x07060302u : 0x05040100u;
-                    const uint32_t d0 = __builtin_amdgcn_perm(rb[g][1][c / 2], rb[g][0][c / 2], sel);
-                    const uint32_t d1 = __builtin_amdgcn_perm(rb[g][3][c / 2], rb[g][2][c / 2], sel);
-                    *reinterpret_cast<pc_u32x2*>(Bs + (nc + c) * PC_ROW + kg * 4) = pc_u32x2{d0, d1};
-                }
+                for (int c = 0; c < 4; ++c)
+                    static_for<P>([&](auto ip) {
+                        constexpr int p = decltype(ip)::value;
+                        *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + (nc + c) * PC_ROW + kg * 4) =
+                            pc_u32x2{b_pair(ip, safe, g, c, 0), b_pair(ip, safe, g, c, 1)};
+                    });
             }
-        } else {
-            uint32_t xa[A_CH][4], xb[B_GR][4][4];   // values: A [chunk][element], B [group][k-row][column]
+        };
+        if constexpr (LD::SPECIALS) {
+            // A wave takes the forms that handle Inf and NaN only when one of
+            // its values of this step is one (a wave-uniform branch).  The test
+            // runs on the piece-0 pairs (top halves): a half shifted left by one
+            // is at least 0xFF00 exactly when its exponent field is all ones.
+            typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
+            u16x2_t mx = {0, 0};
 #pragma unroll
-            for (int i = 0; i < A_CH; ++i) LD::values(ra[i], sa[i], xa[i]);
+            for (int i = 0; i < A_CH; ++i)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    mx = __builtin_elementwise_max(
+                        mx, __builtin_bit_cast(u16x2_t, a_pair(std::integral_constant<int, 0>{}, std::false_type{}, i, h) << 1));
 #pragma unroll
             for (int g = 0; g < B_GR; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) LD::values(rb[g][r], sb[g], xb[g][r]);
-            // piece pairs: A along its chunk, B down its 4 k-rows
-            auto a_pair = [&](auto ip, auto safe, int i, int h) {
-                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xa[i][2 * h], xa[i][2 * h + 1]);
-            };
-            auto b_pair = [&](auto ip, auto safe, int g, int c, int h) {
-                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][2 * h][c], xb[g][2 * h + 1][c]);
-            };
-            auto put = [&](auto safe) {
-#pragma unroll
-                for (int i = 0; i < A_CH; ++i) {
-                    const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
-                    static_for<P>([&](auto ip) {
-                        constexpr int p = decltype(ip)::value;
-                        *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + row * PC_ROW + kc * 4) =
-                            pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
-                    });
-                }
-#pragma unroll
-                for (int g = 0; g < B_GR; ++g) {
-                    const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        static_for<P>([&](auto ip) {
-                            constexpr int p = decltype(ip)::value;
-                            *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + (nc + c) * PC_ROW + kg * 4) =
-                                pc_u32x2{b_pair(ip, safe, g, c, 0), b_pair(ip, safe, g, c, 1)};
-                        });
-                }
-            };
-            if constexpr (LD::SPECIALS) {
-                // A wave takes the forms that handle Inf and NaN only when one of
-                // its values of this step is one (a wave-uniform branch).  The test
-                // runs on the piece-0 pairs (top halves): a half shifted left by one
-                // is at least 0xFF00 exactly when its exponent field is all ones.
-                typedef unsigned short u16x2_t __attribute__((ext_vector_type(2)));
-                u16x2_t mx = {0, 0};
-#pragma unroll
-                for (int i = 0; i < A_CH; ++i)
+                for (int c = 0; c < 4; ++c)
 #pragma unroll
                     for (int h = 0; h < 2; ++h)
                         mx = __builtin_elementwise_max(
-                            mx, __builtin_bit_cast(u16x2_t, a_pair(std::integral_constant<int, 0>{}, std::false_type{}, i, h) << 1));
-#pragma unroll
-                for (int g = 0; g < B_GR; ++g)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-#pragma unroll
-                        for (int h = 0; h < 2; ++h)
-                            mx = __builtin_elementwise_max(
-                                mx, __builtin_bit_cast(u16x2_t,
-                                                       b_pair(std::integral_constant<int, 0>{}, std::false_type{}, g, c, h) << 1));
-                const bool special = mx.x >= 0xFF00 || mx.y >= 0xFF00;
-                if (__builtin_amdgcn_ballot_w64(special)) put(std::true_type{});
-                else put(std::false_type{});
-            } else {
-                put(std::false_type{});
-            }
+                            mx, __builtin_bit_cast(u16x2_t,
+                                                   b_pair(std::integral_constant<int, 0>{}, std::false_type{}, g, c, h) << 1));
+            const bool special = mx.x >= 0xFF00 || mx.y >= 0xFF00;
+            if (__builtin_amdgcn_ballot_w64(special)) put(std::true_type{});
+            else put(std::false_type{});
+        } else {
+            put(std::false_type{});
         }
     };
 
