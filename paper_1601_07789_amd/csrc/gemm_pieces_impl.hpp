@@ -28,10 +28,21 @@
 // Tiling: BM x BN x 32 per workgroup, WGM x WGN waves each (BM/WGM) x
 // (BN/WGN) of v_mfma_f32_16x16x32_bf16 tiles; double-buffered LDS, one
 // barrier per K step, the next step's global loads issued before the current
-// step's MFMAs.  A is kept row-major in LDS and B n-major (k contiguous): a
-// thread loads 4 k-rows x 4 columns of B and transposes the pieces with
-// v_perm_b32, so every MFMA operand is one ds_read_b128.  LDS rows are
-// padded by 16 bytes.  Shapes need not be tile multiples: edge tiles and the
+// step's MFMAs.  Two LDS layouts, chosen by the loader (KMAJOR_B):
+//  - k-major B (the binary64 pieces): A piece planes m-major (k contiguous;
+//    16-byte chunk c of row R at c ^ ((R >> 2) & 3)), read with ds_read_b128;
+//    B piece planes k-major as B is stored (16-byte chunk c of k-row R at
+//    c ^ 2 g(R), g(R) = (R & 3) | ((R >> 1) & 4)), a thread forming the pairs
+//    of 4 columns of each of its 4 k-rows, and each B operand read with two
+//    transposing LDS reads (ds_read_b64_tr_b16).  The swizzles put the 16
+//    lanes of an A read phase and the 8 k-rows of a transposing read phase on
+//    distinct banks, and every store instruction covers whole rows.
+//  - n-major B ({32,3}): rows padded by 16 bytes, B pairs formed down the
+//    group's 4 k-rows (so no separate transposition), every operand one
+//    ds_read_b128.  The {32,3} loader needs more registers for its special
+//    values, and there the k-major layout's extra address registers cost
+//    spills (3-product 383 -> 295 TFLOP/s at 8192^3).
+// Shapes need not be tile multiples: edge tiles and the
 // last K step load with bounds (elements outside the matrix read as +0, and
 // the bytes past a row's last element are never read), and C is stored only
 // inside the matrix.
@@ -48,9 +59,12 @@ typedef __bf16 pc_bf16x2 __attribute__((ext_vector_type(2)));
 typedef float pc_f32x4 __attribute__((ext_vector_type(4)));
 typedef float pc_f32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t pc_u32x2 __attribute__((ext_vector_type(2)));
+typedef short pc_i16x4 __attribute__((ext_vector_type(4)));
+typedef short pc_i16x8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) pc_i16x4 pc_lds_i16x4;
 
 constexpr int PC_BK = 32;            // K per stage: one MFMA
-constexpr int PC_ROW = PC_BK + 8;    // bfloat16 per padded LDS row
+constexpr int PC_ROW = PC_BK + 8;    // bfloat16 per padded LDS row (n-major layout)
 constexpr int PC_SPREAD = 40;        // largest exponent spread a scaled row or column may have
 
 __host__ __device__ constexpr int pc_min(int a, int b) { return a < b ? a : b; }
@@ -82,7 +96,7 @@ __device__ __forceinline__ uint32_t pc_top_pair(uint32_t a, uint32_t b)
 
 struct PcB32K3 {
     static constexpr int KB = 3, PIECES = 2, ROUND_P = 1;
-    static constexpr bool SCALED = false, SPECIALS = true;
+    static constexpr bool SCALED = false, SPECIALS = true, KMAJOR_B = false;
     __device__ static void values(const uint32_t (&d)[3], const int32_t (&)[4], uint32_t (&x)[4])
     {
         unpack_elems<Fmt<32, 3>, 4>(d, x);
@@ -108,7 +122,7 @@ struct PcB32K3 {
 template <int K>
 struct PcB64 {
     static constexpr int KB = K, PIECES = K - 1, ROUND_P = -1;
-    static constexpr bool SCALED = true, SPECIALS = false;
+    static constexpr bool SCALED = true, SPECIALS = false, KMAJOR_B = true;
     __device__ static void values(const uint32_t (&d)[K], const int32_t (&shift)[4], uint32_t (&x)[4])
     {
         uint64_t u[4];
@@ -197,12 +211,14 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
 {
     constexpr int THREADS = 64 * WGM * WGN, P = LD::PIECES, KB = LD::KB;
     constexpr int TM = BM / WGM, TN = BN / WGN, FM = TM / 16, FN = TN / 16;
-    constexpr int A_TILE = BM * PC_ROW, B_TILE = BN * PC_ROW, STAGE = P * (A_TILE + B_TILE);
+    constexpr bool KM = LD::KMAJOR_B;
+    constexpr int A_TILE = BM * (KM ? PC_BK : PC_ROW), B_TILE = KM ? PC_BK * BN : BN * PC_ROW, STAGE = P * (A_TILE + B_TILE);
     constexpr int A_CH = BM * (PC_BK / 4) / THREADS;            // A chunks (4 elements of a row) per thread
     constexpr int B_GR = (PC_BK / 4) * (BN / 4) / THREADS;      // B groups (4 k-rows x 4 columns) per thread
     static_assert(A_CH * THREADS == BM * (PC_BK / 4) && A_CH >= 1, "A staging must divide evenly");
     static_assert(B_GR * THREADS == (PC_BK / 4) * (BN / 4) && B_GR >= 1, "B staging must divide evenly");
     static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile");
+    static_assert(!KM || BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
     static_assert(STAGE * 2 * 2 <= 160 * 1024, "LDS");
     static_assert(OUTK == 0 || LD::SCALED, "packed binary64 C comes from scaled operands");
     // The accumulators go to AGPRs (an empty statement that clobbers one makes
@@ -312,8 +328,13 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
         auto a_pair = [&](auto ip, auto safe, int i, int h) {
             return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xa[i][2 * h], xa[i][2 * h + 1]);
         };
-        auto b_pair = [&](auto ip, auto safe, int g, int c, int h) {
-            return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][2 * h][c], xb[g][2 * h + 1][c]);
+        // B pairs: k-major, columns (2h, 2h + 1) of k-row r of the group; n-major, k-rows (2h, 2h + 1)
+        // of column r
+        auto b_pair = [&](auto ip, auto safe, int g, int r, int h) {
+            if constexpr (KM)
+                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][r][2 * h], xb[g][r][2 * h + 1]);
+            else
+                return pc_pair<LD, decltype(ip)::value, decltype(safe)::value>(xb[g][2 * h][r], xb[g][2 * h + 1][r]);
         };
         auto put = [&](auto safe) {
 #pragma unroll
@@ -321,20 +342,23 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
                 const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
                 static_for<P>([&](auto ip) {
                     constexpr int p = decltype(ip)::value;
-                    *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + row * PC_ROW + kc * 4) =
-                        pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
+                    const int ao = KM ? row * PC_BK + ((kc >> 1) ^ ((row >> 2) & 3)) * 8 + (kc & 1) * 4 : row * PC_ROW + kc * 4;
+                    *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + ao) = pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
                 });
             }
 #pragma unroll
             for (int g = 0; g < B_GR; ++g) {
                 const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
+                for (int r = 0; r < 4; ++r) {
+                    // k-major: k-row kg * 4 + r, columns nc .. nc + 3; n-major: column nc + r, k-rows kg * 4 ..
+                    const int kr = kg * 4 + r, gr = (kr & 3) | ((kr >> 1) & 4);
+                    const int bo = KM ? kr * BN + ((nc >> 3) ^ (2 * gr)) * 8 + (nc & 7) : (nc + r) * PC_ROW + kg * 4;
                     static_for<P>([&](auto ip) {
                         constexpr int p = decltype(ip)::value;
-                        *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + (nc + c) * PC_ROW + kg * 4) =
-                            pc_u32x2{b_pair(ip, safe, g, c, 0), b_pair(ip, safe, g, c, 1)};
+                        *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + bo) = pc_u32x2{b_pair(ip, safe, g, r, 0), b_pair(ip, safe, g, r, 1)};
                     });
+                }
             }
         };
         if constexpr (LD::SPECIALS) {
@@ -353,12 +377,12 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
 #pragma unroll
             for (int g = 0; g < B_GR; ++g)
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
+                for (int r = 0; r < 4; ++r)
 #pragma unroll
                     for (int h = 0; h < 2; ++h)
                         mx = __builtin_elementwise_max(
                             mx, __builtin_bit_cast(u16x2_t,
-                                                   b_pair(std::integral_constant<int, 0>{}, std::false_type{}, g, c, h) << 1));
+                                                   b_pair(std::integral_constant<int, 0>{}, std::false_type{}, g, r, h) << 1));
             const bool special = mx.x >= 0xFF00 || mx.y >= 0xFF00;
             if (__builtin_amdgcn_ballot_w64(special)) put(std::true_type{});
             else put(std::false_type{});
@@ -373,21 +397,36 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
 #pragma unroll
         for (int j = 0; j < FN; ++j) acc[i][j] = pc_f32x4{0.f, 0.f, 0.f, 0.f};
 
+    // fragment offsets within a plane: A row r16 of each 16-row block, chunk lane / 16 (swizzled);
+    // B transposing reads: lane s of a 16-lane group addresses k-row 8 (lane / 16) + s / 4 (+ 4
+    // for the upper half), columns 4 (s % 4) .. + 3 of the 16-column block (swizzled by g of the row)
+    // (n-major: row / column r16 of each 16 block, k offset 8 (lane / 16))
+    const int r16 = lane % 16;
+    const int a_lane = KM ? (wm * TM + r16) * PC_BK + (((lane / 16) ^ ((r16 >> 2) & 3)) * 8)
+                          : (wm * TM + r16) * PC_ROW + 8 * (lane / 16);
+    const int b_lane = KM ? (8 * (lane / 16) + r16 / 4) * BN + 4 * (r16 % 4) : (wn * TN + r16) * PC_ROW + 8 * (lane / 16);
+    const int bg = (r16 / 4) | (((lane / 16) & 1) << 2);
     auto compute = [&](int s) {
-        const int r16 = lane % 16, kq = 8 * (lane / 16);
         pc_bf16x8 a[P][FM], b[P][FN];
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int i = 0; i < FM; ++i)
-                a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + (wm * TM + i * 16 + r16) * PC_ROW + kq);
+                a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + a_lane + i * 16 * (KM ? PC_BK : PC_ROW));
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
-                b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE +
-                                                              (wn * TN + j * 16 + r16) * PC_ROW + kq);
+            for (int j = 0; j < FN; ++j) {
+                if constexpr (KM) {
+                    const uint16_t* q = lds[s] + P * A_TILE + p * B_TILE + b_lane + ((wn * FN + j) ^ bg) * 16;
+                    const pc_i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((pc_lds_i16x4*)(q));
+                    const pc_i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((pc_lds_i16x4*)(q + 4 * BN));
+                    b[p][j] = __builtin_bit_cast(pc_bf16x8, pc_i16x8(__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7)));
+                } else {
+                    b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE + b_lane + j * 16 * PC_ROW);
+                }
+            }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
