@@ -383,6 +383,33 @@ def test_gemm_ragged_binary32(dev, orc, case, shape):
     assert np.all(np.abs(Ch[:, :N].reshape(-1) - ce) <= bound * cab)
 
 
+@pytest.mark.parametrize("shape", [(4100, 4104, 333), (4097, 4099, 70)])
+def test_gemm_bf16_large_edges(dev, orc, shape):
+    """{32,2} shapes large enough for 256 x 256 tiles that are not tile multiples:
+    N a multiple of 8 (rows and column chunks clamped, partial last K step) and N
+    not (the chunk N cuts read by elements).  Entries of the edge rows and columns
+    and random ones within the bound, C's padding columns untouched."""
+    import torch
+    M, N, K = shape
+    log(f"gemm bf16 large edges {shape}")
+    lda, ldb, ldc = K + 2 - K % 2, N + 4 - N % 2, N + 3   # rows of A and B start 4-byte aligned
+    g = np.random.default_rng(M + 3 * N + K)
+    A = orc.pack(32, 2, g.standard_normal(M * lda).astype(np.float32))
+    B = orc.pack(32, 2, g.standard_normal(K * ldb).astype(np.float32))
+    C = torch.full((M * ldc,), 7.0, dtype=torch.float32, device=dev)
+    flyte.gemm((32, 2), (32, 2), (32, 4), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), C=C,
+               lda=lda, ldb=ldb, ldc=ldc)
+    Ch = C.cpu().numpy().reshape(M, ldc).astype(np.float64)
+    assert np.all(Ch[:, N:] == 7.0)
+    rows = np.array([0, 1, 255, 256, 4095, 4096, M - 2, M - 1])
+    cols = np.array([0, 7, 255, 256, 4095, 4096, N - 2, N - 1])
+    gi, gj = np.meshgrid(rows, cols, indexing="ij")
+    ii = np.concatenate([gi.reshape(-1), g.integers(0, M, 512)])
+    jj = np.concatenate([gj.reshape(-1), g.integers(0, N, 512)])
+    ce, cab = orc.gemm_entries((32, 2), (32, 2), K, A, lda, B, ldb, ii, jj)
+    assert np.all(np.abs(Ch[ii, jj] - ce) <= gam(K, U32) * cab)
+
+
 @pytest.mark.parametrize("kin,kout", [(5, 5), (6, 8), (8, 3), (3, 7)])
 @pytest.mark.parametrize("shape", [(300, 520, 333), (129, 1, 17), (1, 130, 250)])
 def test_gemm_ragged_f64(dev, orc, kin, kout, shape):
