@@ -129,12 +129,11 @@ struct PcB64 {
         unpack_elems<Fmt<64, K>, 4>(d, u);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const uint32_t h = (uint32_t)(u[e] >> 32);   // sign, 11-bit exponent, top 20 mantissa bits
-            // exponent E -> E - e_ref + 127 in place (in [87, 127] for a row that
-            // can be scaled), then moved to binary32's 8-bit field
-            const uint32_t t = h - (uint32_t)shift[e];
-            const uint32_t f = (h & 0x80000000u) | ((t << 3) & 0x7FFFFFFFu);
-            x[e] = (h & 0x7FFFFFFFu) ? f : h;    // signed zeros stay zeros
+            // the element (its low word is zero for K <= 4) times 2^(1023 - e_ref), exact, then
+            // to binary32, exact for a row that can be scaled (the scaled value lies in
+            // [2^-40, 2) with at most 21 significant bits); zeros stay signed zeros
+            const double v = __builtin_amdgcn_ldexp(__longlong_as_double((long long)u[e]), 896 - (shift[e] >> 20));
+            x[e] = __float_as_uint((float)v);
         }
     }
     template <int PC, bool SAFE>
