@@ -407,12 +407,14 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     const int bg = (r16 / 4) | (((lane / 16) & 1) << 2);
     auto compute = [&](int s) {
         pc_bf16x8 a[P][FM], b[P][FN];
+        auto read_a = [&](int p, int i) {
+            a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + a_lane + i * 16 * (KM ? PC_BK : PC_ROW));
+        };
         __builtin_amdgcn_s_setprio(1);
+        // the first row block of A and all of B first, so the MFMAs of row block 0 start
+        // after those reads while the rest of A arrives
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + a_lane + i * 16 * (KM ? PC_BK : PC_ROW));
+        for (int p = 0; p < P; ++p) read_a(p, 0);
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
@@ -426,6 +428,10 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
                     b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE + b_lane + j * 16 * PC_ROW);
                 }
             }
+#pragma unroll
+        for (int i = 1; i < FM; ++i)
+#pragma unroll
+            for (int p = 0; p < P; ++p) read_a(p, i);
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
