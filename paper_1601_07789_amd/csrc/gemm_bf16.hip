@@ -78,7 +78,7 @@ struct B32Tile {
     static_assert(BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
 };
 
-__device__ __forceinline__ int pc_clamp8(int v) { return v < 0 ? 0 : (v > 8 ? 8 : v); }
+__device__ __forceinline__ int clamp8(int v) { return v < 0 ? 0 : (v > 8 ? 8 : v); }
 
 // 8 bfloat16 from p, element e read only when e < nvalid (else zero; nvalid may be <= 0).
 __device__ __forceinline__ u32x4_t load8_edge(const uint8_t* p, int nvalid)
@@ -127,7 +127,7 @@ k_gemm_b32(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict
         return (int64_t)(EDGE == 1 && col >= N ? N - 8 : col);
     };
     // elements of B's chunk i inside the matrix (EDGE = 2: N cuts a chunk), 0..8
-    auto b_valid = [&](int i) { return pc_clamp8(N - (n0 + ((t + THREADS * i) % T::BCPR) * 8)); };
+    auto b_valid = [&](int i) { return clamp8(N - (n0 + ((t + THREADS * i) % T::BCPR) * 8)); };
 
     // a full K step at k0
     auto load_tiles = [&](int k0) {
