@@ -26,9 +26,9 @@ template <class F>
 static fb_status launch_gemv(const GemvArgs& a, int tile, hipStream_t stream)
 {
     switch (tile) {
-#define FLYTE_TILE_LAUNCH(ID, LPR, RPW, U, KS, NT, ST)                                       \
+#define FLYTE_TILE_LAUNCH(ID, LPR, RPW, U, KS, NT, ST, PP)                                   \
     case ID: {                                                                               \
-        using TL = GemvTile<LPR, RPW, U, KS, NT, ST>;                                        \
+        using TL = GemvTile<LPR, RPW, U, KS, NT, ST, PP>;                                    \
         const int64_t blocks = (a.m + TL::rows_per_block - 1) / TL::rows_per_block;          \
         k_gemv<F, TL><<<(unsigned)blocks, kGemvBlock, 0, stream>>>(a);                       \
         return check_launch("fb_gemv");                                                      \
@@ -46,9 +46,9 @@ const void* gemv_kernel_fn(fb_format f, int tile, int64_t m, unsigned* blocks)
     return dispatch_format(f, [&](auto tag) -> const void* {
         using F = Fmt<decltype(tag.first)::value, decltype(tag.second)::value>;
         switch (tile) {
-#define FLYTE_TILE_FN(ID, LPR, RPW, U, KS, NT, ST)                                         \
+#define FLYTE_TILE_FN(ID, LPR, RPW, U, KS, NT, ST, PP)                                     \
     case ID: {                                                                             \
-        using TL = GemvTile<LPR, RPW, U, KS, NT, ST>;                                      \
+        using TL = GemvTile<LPR, RPW, U, KS, NT, ST, PP>;                                  \
         *blocks = (unsigned)((m + TL::rows_per_block - 1) / TL::rows_per_block);           \
         return reinterpret_cast<const void*>(k_gemv<F, TL>);                               \
     }

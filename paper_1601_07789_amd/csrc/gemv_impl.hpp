@@ -13,7 +13,9 @@
 // a fixed xor butterfly, then the KS wave partials in a fixed order through
 // LDS, so every result is a fixed sequence of base-type operations for a
 // given tile configuration.  NT marks the A loads non-temporal (A is read
-// once; x should stay cached).
+// once; x should stay cached).  PIPE software-pipelines the unit loop: the
+// next trip's loads are issued before this trip's FMAs, into a second set of
+// registers (the same operations in the same order, so the same results).
 #pragma once
 
 #include "codec.hpp"
@@ -33,12 +35,13 @@ struct GemvArgs {
     int32_t ymode;         // rounding mode of a packed y
 };
 
-template <int LPR, int RPW, int U, int KS = 1, bool NT = false, bool STAGED = false>
+template <int LPR, int RPW, int U, int KS = 1, bool NT = false, bool STAGED = false, bool PIPE = false>
 struct GemvTile {
     static_assert(KS == 1 || KS == 2 || KS == 4, "waves per row group");
     static_assert(!STAGED || LPR == 64, "staged tiles use whole waves per row group");
+    static_assert(!(STAGED && PIPE), "the staged sweep is not pipelined");
     static constexpr int lpr = LPR, rpw = RPW, u = U, ks = KS;
-    static constexpr bool nt = NT, staged = STAGED;
+    static constexpr bool nt = NT, staged = STAGED, pipe = PIPE;
     static constexpr int rows_per_wave = (64 / LPR) * RPW;
     static constexpr int rows_per_block = (kGemvWaves / KS) * rows_per_wave;
 };
@@ -148,9 +151,8 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
         unit0 = nspans * (1024 / F::UNIT);
     }
 
-    for (int64_t g0 = unit0 + sl; g0 < nunits; g0 += (int64_t)KS * LPR * U) {
-        uint32_t X[U][F::UNIT_NW];
-        uint32_t P[RPW][U][F::UNIT_DW];
+    // one trip: U units of every row (and of x) per lane
+    auto load_trip = [&](int64_t g0, uint32_t (&X)[U][F::UNIT_NW], uint32_t (&P)[RPW][U][F::UNIT_DW]) {
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + (int64_t)u * KS * LPR;
@@ -163,6 +165,8 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
                 }
             }
         });
+    };
+    auto fma_trip = [&](int64_t g0, uint32_t (&X)[U][F::UNIT_NW], uint32_t (&P)[RPW][U][F::UNIT_DW]) {
         static_for<U>([&](auto iu) {
             constexpr int u = decltype(iu)::value;
             const int64_t g = g0 + (int64_t)u * KS * LPR;
@@ -179,6 +183,28 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
                 }
             }
         });
+    };
+    constexpr int64_t STEP = (int64_t)KS * LPR * U;
+    if constexpr (TILE::pipe) {
+        // two register sets, alternating: trip t + 1 is in flight while trip t is summed
+        uint32_t Xa[U][F::UNIT_NW], Pa[RPW][U][F::UNIT_DW], Xb[U][F::UNIT_NW], Pb[RPW][U][F::UNIT_DW];
+        int64_t g0 = unit0 + sl;
+        if (g0 < nunits) load_trip(g0, Xa, Pa);
+        while (g0 < nunits) {
+            if (g0 + STEP < nunits) load_trip(g0 + STEP, Xb, Pb);
+            fma_trip(g0, Xa, Pa);
+            g0 += STEP;
+            if (g0 >= nunits) break;
+            if (g0 + STEP < nunits) load_trip(g0 + STEP, Xa, Pa);
+            fma_trip(g0, Xb, Pb);
+            g0 += STEP;
+        }
+    } else {
+        for (int64_t g0 = unit0 + sl; g0 < nunits; g0 += STEP) {
+            uint32_t X[U][F::UNIT_NW], P[RPW][U][F::UNIT_DW];
+            load_trip(g0, X, P);
+            fma_trip(g0, X, P);
+        }
     }
     // columns after the last whole unit: one element per lane
     {
@@ -233,50 +259,54 @@ __device__ __forceinline__ void gemv_block(const GemvArgs& a, int64_t tile_row0)
 
 // The tile configurations, in index order (the index is the public config
 // id): (lanes per row group, rows per lane group, units per lane per trip,
-// waves per row group, non-temporal A loads, LDS byte staging).
-#define FLYTE_GEMV_TILES(X)          \
-    X(0, 64, 1, 2, 1, false, false)         \
-    X(1, 64, 1, 4, 1, false, false)         \
-    X(2, 64, 2, 2, 1, false, false)         \
-    X(3, 64, 2, 4, 1, false, false)         \
-    X(4, 64, 4, 1, 1, false, false)         \
-    X(5, 64, 4, 2, 1, false, false)         \
-    X(6, 64, 8, 1, 1, false, false)         \
-    X(7, 32, 2, 2, 1, false, false)         \
-    X(8, 16, 1, 2, 1, false, false)         \
-    X(9, 16, 2, 2, 1, false, false)         \
-    X(10, 16, 4, 1, 1, false, false)        \
-    X(11, 8, 2, 1, 1, false, false)         \
-    X(12, 8, 4, 1, 1, false, false)         \
-    X(13, 64, 2, 2, 2, false, false)        \
-    X(14, 64, 4, 1, 2, false, false)        \
-    X(15, 64, 4, 2, 2, false, false)        \
-    X(16, 64, 2, 2, 4, false, false)        \
-    X(17, 64, 4, 1, 4, false, false)        \
-    X(18, 64, 8, 1, 4, false, false)        \
-    X(19, 64, 4, 2, 1, true, false)         \
-    X(20, 64, 2, 4, 1, true, false)         \
-    X(21, 64, 4, 1, 2, true, false)         \
-    X(22, 64, 4, 1, 4, true, false)         \
-    X(23, 64, 1, 1, 1, true, true)          \
-    X(24, 64, 2, 1, 1, true, true)          \
-    X(25, 64, 4, 1, 1, true, true)          \
-    X(26, 64, 2, 1, 2, true, true)          \
-    X(27, 64, 4, 1, 2, true, true)          \
-    X(28, 64, 2, 1, 4, true, true)          \
-    X(29, 64, 4, 1, 4, true, true)          \
-    X(30, 64, 8, 1, 4, true, true)          \
-    X(31, 32, 2, 2, 1, true, false)         \
-    X(32, 16, 2, 2, 1, true, false)         \
-    X(33, 8, 2, 1, 1, true, false)          \
-    X(34, 64, 1, 2, 4, true, false)         \
-    X(35, 64, 1, 4, 4, true, false)         \
-    X(36, 64, 2, 2, 4, true, false)         \
-    X(37, 64, 1, 1, 4, true, true)          \
-    X(38, 64, 8, 2, 4, true, false)         \
-    X(39, 64, 4, 2, 2, true, false)
+// waves per row group, non-temporal A loads, LDS byte staging, pipelined).
+#define FLYTE_GEMV_TILES(X)                   \
+    X(0, 64, 1, 2, 1, false, false, false)    \
+    X(1, 64, 1, 4, 1, false, false, false)    \
+    X(2, 64, 2, 2, 1, false, false, false)    \
+    X(3, 64, 2, 4, 1, false, false, false)    \
+    X(4, 64, 4, 1, 1, false, false, false)    \
+    X(5, 64, 4, 2, 1, false, false, false)    \
+    X(6, 64, 8, 1, 1, false, false, false)    \
+    X(7, 32, 2, 2, 1, false, false, false)    \
+    X(8, 16, 1, 2, 1, false, false, false)    \
+    X(9, 16, 2, 2, 1, false, false, false)    \
+    X(10, 16, 4, 1, 1, false, false, false)   \
+    X(11, 8, 2, 1, 1, false, false, false)    \
+    X(12, 8, 4, 1, 1, false, false, false)    \
+    X(13, 64, 2, 2, 2, false, false, false)   \
+    X(14, 64, 4, 1, 2, false, false, false)   \
+    X(15, 64, 4, 2, 2, false, false, false)   \
+    X(16, 64, 2, 2, 4, false, false, false)   \
+    X(17, 64, 4, 1, 4, false, false, false)   \
+    X(18, 64, 8, 1, 4, false, false, false)   \
+    X(19, 64, 4, 2, 1, true, false, false)    \
+    X(20, 64, 2, 4, 1, true, false, false)    \
+    X(21, 64, 4, 1, 2, true, false, false)    \
+    X(22, 64, 4, 1, 4, true, false, false)    \
+    X(23, 64, 1, 1, 1, true, true, false)     \
+    X(24, 64, 2, 1, 1, true, true, false)     \
+    X(25, 64, 4, 1, 1, true, true, false)     \
+    X(26, 64, 2, 1, 2, true, true, false)     \
+    X(27, 64, 4, 1, 2, true, true, false)     \
+    X(28, 64, 2, 1, 4, true, true, false)     \
+    X(29, 64, 4, 1, 4, true, true, false)     \
+    X(30, 64, 8, 1, 4, true, true, false)     \
+    X(31, 32, 2, 2, 1, true, false, false)    \
+    X(32, 16, 2, 2, 1, true, false, false)    \
+    X(33, 8, 2, 1, 1, true, false, false)     \
+    X(34, 64, 1, 2, 4, true, false, false)    \
+    X(35, 64, 1, 4, 4, true, false, false)    \
+    X(36, 64, 2, 2, 4, true, false, false)    \
+    X(37, 64, 1, 1, 4, true, true, false)     \
+    X(38, 64, 8, 2, 4, true, false, false)    \
+    X(39, 64, 4, 2, 2, true, false, false)    \
+    X(40, 64, 8, 2, 4, true, false, true)     \
+    X(41, 64, 2, 2, 4, true, false, true)     \
+    X(42, 64, 4, 2, 2, true, false, true)     \
+    X(43, 64, 4, 2, 1, true, false, true)
 
-constexpr int kGemvNumTiles = 40;
+constexpr int kGemvNumTiles = 44;
 
 struct TileInfo {
     int lpr, rpw, u, ks, nt, staged, rows_per_block;
@@ -285,8 +315,8 @@ struct TileInfo {
 inline TileInfo gemv_tile_info(int id)
 {
     switch (id) {
-#define FLYTE_TILE_CASE(ID, LPR, RPW, U, KS, NT, ST) \
-    case ID: return TileInfo{LPR, RPW, U, KS, NT, ST, GemvTile<LPR, RPW, U, KS, NT, ST>::rows_per_block};
+#define FLYTE_TILE_CASE(ID, LPR, RPW, U, KS, NT, ST, PP) \
+    case ID: return TileInfo{LPR, RPW, U, KS, NT, ST, GemvTile<LPR, RPW, U, KS, NT, ST, PP>::rows_per_block};
         FLYTE_GEMV_TILES(FLYTE_TILE_CASE)
 #undef FLYTE_TILE_CASE
     }
