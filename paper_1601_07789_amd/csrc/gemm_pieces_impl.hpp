@@ -28,20 +28,24 @@
 // Tiling: BM x BN x 32 per workgroup, WGM x WGN waves each (BM/WGM) x
 // (BN/WGN) of v_mfma_f32_16x16x32_bf16 tiles; double-buffered LDS, one
 // barrier per K step, the next step's global loads issued before the current
-// step's MFMAs.  Two LDS layouts, chosen by the loader (KMAJOR_B):
-//  - k-major B (the binary64 pieces): A piece planes m-major (k contiguous;
-//    16-byte chunk c of row R at c ^ ((R >> 2) & 3)), read with ds_read_b128;
-//    B piece planes k-major as B is stored (16-byte chunk c of k-row R at
-//    c ^ 2 g(R), g(R) = (R & 3) | ((R >> 1) & 4)), a thread forming the pairs
-//    of 4 columns of each of its 4 k-rows, and each B operand read with two
-//    transposing LDS reads (ds_read_b64_tr_b16).  The swizzles put the 16
-//    lanes of an A read phase and the 8 k-rows of a transposing read phase on
-//    distinct banks, and every store instruction covers whole rows.
-//  - n-major B ({32,3}): rows padded by 16 bytes, B pairs formed down the
-//    group's 4 k-rows (so no separate transposition), every operand one
-//    ds_read_b128.  The {32,3} loader needs more registers for its special
-//    values, and there the k-major layout's extra address registers cost
-//    spills (3-product 383 -> 295 TFLOP/s at 8192^3).
+// step's MFMAs.  A piece planes are m-major (k contiguous, unpadded; 16-byte
+// chunk c of row R at c ^ ((R >> 2) & 3)), read with ds_read_b128.  Two B
+// layouts, chosen by the loader (KMAJOR_B):
+//  - k-major B (the binary64 pieces): B piece planes k-major as B is stored
+//    (16-byte chunk c of k-row R at c ^ 2 g(R), g(R) = (R & 3) | ((R >> 1) &
+//    4)), a thread forming the pairs of 4 columns of each of its 4 k-rows,
+//    and each B operand read with two transposing LDS reads
+//    (ds_read_b64_tr_b16).
+//  - n-major B ({32,3}): B pairs formed down the group's 4 k-rows (so no
+//    separate transposition), every operand one ds_read_b128.  Column n of
+//    the tile goes to plane n % 4, row n / 4 (rows padded to 80 bytes, planes
+//    64 bytes apart), so the 64 lanes of a store instruction (4 columns apart)
+//    write consecutive rows.  The {32,3} loader needs more registers for its
+//    special values, and there the k-major layout's extra address registers
+//    cost spills (3-product 383 -> 295 TFLOP/s at 8192^3).
+// The swizzles and the plane offset put the 16 lanes of a read phase (and the
+// 8 k-rows of a transposing read phase) on distinct banks; a store instruction
+// has at most two lanes on one bank per 32-lane phase.
 // Shapes need not be tile multiples: edge tiles and the
 // last K step load with bounds (elements outside the matrix read as +0, and
 // the bytes past a row's last element are never read), and C is stored only
@@ -65,6 +69,7 @@ typedef __attribute__((address_space(3))) pc_i16x4 pc_lds_i16x4;
 
 constexpr int PC_BK = 32;            // K per stage: one MFMA
 constexpr int PC_ROW = PC_BK + 8;    // bfloat16 per padded LDS row (n-major layout)
+constexpr int PC_PLANE_PAD = 32;     // bfloat16 between the four column planes of an n-major B tile
 constexpr int PC_SPREAD = 40;        // largest exponent spread a scaled row or column may have
 
 __host__ __device__ constexpr int pc_min(int a, int b) { return a < b ? a : b; }
@@ -211,13 +216,16 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     constexpr int THREADS = 64 * WGM * WGN, P = LD::PIECES, KB = LD::KB;
     constexpr int TM = BM / WGM, TN = BN / WGN, FM = TM / 16, FN = TN / 16;
     constexpr bool KM = LD::KMAJOR_B;
-    constexpr int A_TILE = BM * (KM ? PC_BK : PC_ROW), B_TILE = KM ? PC_BK * BN : BN * PC_ROW, STAGE = P * (A_TILE + B_TILE);
+    // n-major B: column n of the tile in plane n % 4, row n / 4, the planes BQ apart
+    constexpr int BQ = (BN / 4) * PC_ROW + PC_PLANE_PAD;
+    constexpr int A_TILE = BM * PC_BK, B_TILE = KM ? PC_BK * BN : 4 * BQ, STAGE = P * (A_TILE + B_TILE);
     constexpr int A_CH = BM * (PC_BK / 4) / THREADS;            // A chunks (4 elements of a row) per thread
     constexpr int B_GR = (PC_BK / 4) * (BN / 4) / THREADS;      // B groups (4 k-rows x 4 columns) per thread
     static_assert(A_CH * THREADS == BM * (PC_BK / 4) && A_CH >= 1, "A staging must divide evenly");
     static_assert(B_GR * THREADS == (PC_BK / 4) * (BN / 4) && B_GR >= 1, "B staging must divide evenly");
     static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile");
     static_assert(!KM || BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
+    static_assert(KM || TN % 16 == 0, "n-major B planes hold whole 16-column blocks");
     static_assert(STAGE * 2 * 2 <= 160 * 1024, "LDS");
     static_assert(OUTK == 0 || LD::SCALED, "packed binary64 C comes from scaled operands");
     // The accumulators go to AGPRs (an empty statement that clobbers one makes
@@ -341,7 +349,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
                 const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
                 static_for<P>([&](auto ip) {
                     constexpr int p = decltype(ip)::value;
-                    const int ao = KM ? row * PC_BK + ((kc >> 1) ^ ((row >> 2) & 3)) * 8 + (kc & 1) * 4 : row * PC_ROW + kc * 4;
+                    const int ao = row * PC_BK + ((kc >> 1) ^ ((row >> 2) & 3)) * 8 + (kc & 1) * 4;
                     *reinterpret_cast<pc_u32x2*>(As + p * A_TILE + ao) = pc_u32x2{a_pair(ip, safe, i, 0), a_pair(ip, safe, i, 1)};
                 });
             }
@@ -350,9 +358,10 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
                 const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    // k-major: k-row kg * 4 + r, columns nc .. nc + 3; n-major: column nc + r, k-rows kg * 4 ..
+                    // k-major: k-row kg * 4 + r, columns nc .. nc + 3; n-major: column nc + r (plane r,
+                    // row nc / 4), k-rows kg * 4 ..
                     const int kr = kg * 4 + r, gr = (kr & 3) | ((kr >> 1) & 4);
-                    const int bo = KM ? kr * BN + ((nc >> 3) ^ (2 * gr)) * 8 + (nc & 7) : (nc + r) * PC_ROW + kg * 4;
+                    const int bo = KM ? kr * BN + ((nc >> 3) ^ (2 * gr)) * 8 + (nc & 7) : r * BQ + (nc / 4) * PC_ROW + kg * 4;
                     static_for<P>([&](auto ip) {
                         constexpr int p = decltype(ip)::value;
                         *reinterpret_cast<pc_u32x2*>(Bs + p * B_TILE + bo) = pc_u32x2{b_pair(ip, safe, g, r, 0), b_pair(ip, safe, g, r, 1)};
@@ -399,16 +408,16 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     // fragment offsets within a plane: A row r16 of each 16-row block, chunk lane / 16 (swizzled);
     // B transposing reads: lane s of a 16-lane group addresses k-row 8 (lane / 16) + s / 4 (+ 4
     // for the upper half), columns 4 (s % 4) .. + 3 of the 16-column block (swizzled by g of the row)
-    // (n-major: row / column r16 of each 16 block, k offset 8 (lane / 16))
+    // (n-major: column r16 of each 16 block in plane r16 % 4, k offset 8 (lane / 16))
     const int r16 = lane % 16;
-    const int a_lane = KM ? (wm * TM + r16) * PC_BK + (((lane / 16) ^ ((r16 >> 2) & 3)) * 8)
-                          : (wm * TM + r16) * PC_ROW + 8 * (lane / 16);
-    const int b_lane = KM ? (8 * (lane / 16) + r16 / 4) * BN + 4 * (r16 % 4) : (wn * TN + r16) * PC_ROW + 8 * (lane / 16);
+    const int a_lane = (wm * TM + r16) * PC_BK + (((lane / 16) ^ ((r16 >> 2) & 3)) * 8);
+    const int b_lane = KM ? (8 * (lane / 16) + r16 / 4) * BN + 4 * (r16 % 4)
+                          : (r16 % 4) * BQ + ((wn * TN) / 4 + r16 / 4) * PC_ROW + 8 * (lane / 16);
     const int bg = (r16 / 4) | (((lane / 16) & 1) << 2);
     auto compute = [&](int s) {
         pc_bf16x8 a[P][FM], b[P][FN];
         auto read_a = [&](int p, int i) {
-            a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + a_lane + i * 16 * (KM ? PC_BK : PC_ROW));
+            a[p][i] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + p * A_TILE + a_lane + i * 16 * PC_BK);
         };
         __builtin_amdgcn_s_setprio(1);
         // the first row block of A and all of B first, so the MFMAs of row block 0 start
@@ -425,7 +434,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
                     const pc_i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((pc_lds_i16x4*)(q + 4 * BN));
                     b[p][j] = __builtin_bit_cast(pc_bf16x8, pc_i16x8(__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7)));
                 } else {
-                    b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE + b_lane + j * 16 * PC_ROW);
+                    b[p][j] = *reinterpret_cast<const pc_bf16x8*>(lds[s] + P * A_TILE + p * B_TILE + b_lane + j * 4 * PC_ROW);
                 }
             }
 #pragma unroll
