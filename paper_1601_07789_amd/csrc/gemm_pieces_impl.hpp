@@ -206,9 +206,12 @@ __device__ __forceinline__ uint64_t pc_shfl_u64(uint64_t v, int src)
 // PRODS: bit (pa * P + pb) set = form the product of A piece pa and B piece pb.
 // OUTK = 0: C is FP32 (binary32 operands); else C is packed binary64 in OUTK
 // bytes, rounded in mode RMODE (scaled operands).
-// CHECK: loads and stores are bounded (any M, N, K); without it M, N are
-// multiples of BM, BN and K of 32.
-template <class LD, int PRODS, int BM, int BN, int WGM, int WGN, int OUTK, int RMODE, bool CHECK>
+// EDGE 0: M, N are multiples of BM, BN and K of 32.  EDGE 1: any M, N with N a
+// multiple of 4 and K of 32; rows past M and column groups past N load the
+// last row / column group (whole chunks, so no element of a valid column
+// moves), and C is stored only inside the matrix.  EDGE 2: any M, N, K; loads
+// of edge tiles and of a partial last K step are bounded.
+template <class LD, int PRODS, int BM, int BN, int WGM, int WGN, int OUTK, int RMODE, int EDGE>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
           void* __restrict__ Cv, int64_t ldc, int M, int N, int K, PcScale sc)
@@ -226,6 +229,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     static_assert(TM % 16 == 0 && TN % 16 == 0, "wave tile");
     static_assert(!KM || BN >= 128, "the B swizzle permutes 8 blocks of 16 columns");
     static_assert(KM || TN % 16 == 0, "n-major B planes hold whole 16-column blocks");
+    static_assert(KM || BN % 128 == 0, "n-major B groups: 32 column groups per k-row group pair");
     static_assert(STAGE * 2 * 2 <= 160 * 1024, "LDS");
     static_assert(OUTK == 0 || LD::SCALED, "packed binary64 C comes from scaled operands");
     // The accumulators go to AGPRs (an empty statement that clobbers one makes
@@ -250,20 +254,44 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     }
     const int t = threadIdx.x, lane = t % 64, wid = t / 64;
     const int wm = wid / WGN, wn = wid % WGN;
-    const bool interior = !CHECK || (m0 + BM <= M && n0 + BN <= N);
+    const bool interior = EDGE == 0 || (m0 + BM <= M && n0 + BN <= N);
+
+    // B group gi (4 k-rows x 4 columns) -> its column group and k-row group.  k-major: the
+    // 64 groups of a wave run along the columns of one k-row group.  n-major: each 32-lane
+    // phase of a wave takes 16 column groups of each of two k-row groups, so the 8-byte
+    // stores of one instruction (a row per column, the k-row group's 8 bytes in it) fall on
+    // 64 distinct banks.
+    auto b_cg = [](int gi) {
+        if constexpr (KM) return gi % (BN / 4);
+        return 32 * ((gi / 64) % (BN / 128)) + gi % 16 + 16 * ((gi / 32) % 2);
+    };
+    auto b_kg = [](int gi) {
+        if constexpr (KM) return gi / (BN / 4);
+        return 2 * ((gi / 64) / (BN / 128)) + (gi / 16) % 2;
+    };
+
+    // tile row of A chunk c and first tile column of B group gi, as loaded (EDGE 1: clamped)
+    auto a_row = [&](int c) {
+        const int r = c / (PC_BK / 4);
+        return EDGE == 1 ? pc_min(m0 + r, M - 1) - m0 : r;
+    };
+    auto b_col = [&](int gi) {
+        const int cc = b_cg(gi) * 4;
+        return EDGE == 1 ? pc_min(n0 + cc, N - 4) - n0 : cc;
+    };
 
     // exponent shifts of this thread's A rows and B columns (fixed over K)
     int32_t sa[A_CH][4], sb[B_GR][4];
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
-        const int row = m0 + (t + THREADS * i) / (PC_BK / 4);
+        const int row = m0 + a_row(t + THREADS * i);
         const int32_t v = (LD::SCALED && row < M) ? sc.shiftA[row] : 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) sa[i][e] = v;
     }
 #pragma unroll
     for (int g = 0; g < B_GR; ++g) {
-        const int col = n0 + ((t + THREADS * g) % (BN / 4)) * 4;
+        const int col = n0 + b_col(t + THREADS * g);
 #pragma unroll
         for (int e = 0; e < 4; ++e) sb[g][e] = (LD::SCALED && col + e < N) ? sc.shiftB[col + e] : 0;
     }
@@ -272,25 +300,25 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
 
     // Byte offsets of this thread's chunks from the tile's corner, fixed over
     // K: the per-step address is a wave-uniform base plus these (the host
-    // keeps BM * lda * KB and 32 * ldb * KB below 2^31 for the unchecked form).
+    // keeps BM * lda * KB and 32 * ldb * KB below 2^31 for EDGE 0 and 1).
     uint32_t aoff[A_CH], boff[B_GR][4];
 #pragma unroll
     for (int i = 0; i < A_CH; ++i) {
         const int c = t + THREADS * i;
-        aoff[i] = (uint32_t)((c / (PC_BK / 4)) * lda * KB + (c % (PC_BK / 4)) * 4 * KB);
+        aoff[i] = (uint32_t)(a_row(c) * lda * KB + (c % (PC_BK / 4)) * 4 * KB);
     }
 #pragma unroll
     for (int g = 0; g < B_GR; ++g) {
         const int gi = t + THREADS * g;
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            boff[g][r] = (uint32_t)(((gi / (BN / 4)) * 4 + r) * ldb * KB + (gi % (BN / 4)) * 4 * KB);
+            boff[g][r] = (uint32_t)((b_kg(gi) * 4 + r) * ldb * KB + b_col(gi) * KB);
     }
     const uint8_t* Atile = A + (int64_t)m0 * lda * KB;
     const uint8_t* Btile = B + (int64_t)n0 * KB;
 
     auto load_tiles = [&](int k0) {
-        const bool edge = CHECK && (!interior || k0 + PC_BK > K);
+        const bool edge = EDGE == 2 && (!interior || k0 + PC_BK > K);
         if (!edge) {
             const uint8_t* Ak = Atile + k0 * KB;
             const uint8_t* Bk = Btile + (int64_t)k0 * ldb * KB;
@@ -311,7 +339,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
         }
 #pragma unroll
         for (int g = 0; g < B_GR; ++g) {
-            const int gi = t + THREADS * g, col = n0 + (gi % (BN / 4)) * 4, kr = k0 + (gi / (BN / 4)) * 4;
+            const int gi = t + THREADS * g, col = n0 + b_cg(gi) * 4, kr = k0 + b_kg(gi) * 4;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const uint8_t* p = B + ((int64_t)(kr + r) * ldb + col) * KB;
@@ -355,7 +383,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
             }
 #pragma unroll
             for (int g = 0; g < B_GR; ++g) {
-                const int gi = t + THREADS * g, nc = (gi % (BN / 4)) * 4, kg = gi / (BN / 4);
+                const int gi = t + THREADS * g, nc = b_cg(gi) * 4, kg = b_kg(gi);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     // k-major: k-row kg * 4 + r, columns nc .. nc + 3; n-major: column nc + r (plane r,
@@ -533,15 +561,20 @@ fb_status pc_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, co
     const int64_t blocks = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
     auto a = static_cast<const uint8_t*>(A);
     auto b = static_cast<const uint8_t*>(B);
-    // shapes that are tile multiples (and whose per-tile offsets fit 31 bits)
-    // take the instance without bounds checks
+    // shapes that are tile multiples take the instance without bounds, those
+    // with N a multiple of 4 and K of 32 the clamped one (both need per-tile
+    // offsets that fit 31 bits), the rest the bounded one
     constexpr int KB = LD::KB;
-    if (M % BM == 0 && N % BN == 0 && K % PC_BK == 0 && (int64_t)BM * lda * KB < (1ll << 31) &&
-        (int64_t)PC_BK * ldb * KB < (1ll << 31))
-        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, false><<<(unsigned)blocks, 64 * WGM * WGN, 0, stream>>>(
+    const bool offs = (int64_t)BM * lda * KB < (1ll << 31) && (int64_t)PC_BK * ldb * KB < (1ll << 31);
+    const unsigned grid = (unsigned)blocks, threads = 64 * WGM * WGN;
+    if (offs && M % BM == 0 && N % BN == 0 && K % PC_BK == 0)
+        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, 0><<<grid, threads, 0, stream>>>(
+            a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
+    else if (offs && N % 4 == 0 && K % PC_BK == 0)
+        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, 1><<<grid, threads, 0, stream>>>(
             a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
     else
-        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, true><<<(unsigned)blocks, 64 * WGM * WGN, 0, stream>>>(
+        k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, 2><<<grid, threads, 0, stream>>>(
             a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
     return check_launch("fb_gemm");
 }

@@ -355,7 +355,8 @@ def _ld(n, k):
     return (n + g - 1) // g * g        # rows start 4-byte aligned
 
 
-RAGGED = [(300, 310, 277), (1, 5, 3), (129, 257, 65), (300, 200, 4), (257, 131, 1)]
+# the last two: N a multiple of 4 and K of 32 (edge rows and column groups clamped in the piece kernel)
+RAGGED = [(300, 310, 277), (1, 5, 3), (129, 257, 65), (300, 200, 4), (257, 131, 1), (300, 260, 96), (1, 4, 32)]
 
 
 @pytest.mark.parametrize("case", ["bf16", "three", "four"])
@@ -383,22 +384,31 @@ def test_gemm_ragged_binary32(dev, orc, case, shape):
     assert np.all(np.abs(Ch[:, :N].reshape(-1) - ce) <= bound * cab)
 
 
-@pytest.mark.parametrize("shape", [(4100, 4104, 333), (4097, 4099, 70)])
-def test_gemm_bf16_large_edges(dev, orc, shape):
-    """{32,2} shapes large enough for 256 x 256 tiles that are not tile multiples:
+@pytest.mark.parametrize("case,shape", [("bf16", (4100, 4104, 333)), ("bf16", (4097, 4099, 70)),
+                                        ("three", (4100, 4104, 320)), ("four", (4100, 4104, 320)),
+                                        ("three", (4097, 4099, 70))])
+def test_gemm_bf16_large_edges(dev, orc, case, shape):
+    """Shapes large enough for 256 x 256 tiles that are not tile multiples.  {32,2}:
     N a multiple of 8 (rows and column chunks clamped, partial last K step) and N
-    not (the chunk N cuts read by elements).  Entries of the edge rows and columns
-    and random ones within the bound, C's padding columns untouched."""
+    not (the chunk N cuts read by elements).  {32,3}: N a multiple of 4 and K of 32
+    (rows and column groups clamped) and neither (bounded loads).  Entries of the
+    edge rows and columns and random ones within the bound, C's padding columns
+    untouched."""
     import torch
     M, N, K = shape
-    log(f"gemm bf16 large edges {shape}")
-    lda, ldb, ldc = K + 2 - K % 2, N + 4 - N % 2, N + 3   # rows of A and B start 4-byte aligned
+    log(f"gemm {case} large edges {shape}")
+    k = 2 if case == "bf16" else 3
+    if k == 2:
+        lda, ldb = K + 2 - K % 2, N + 4 - N % 2   # rows of A and B start 4-byte aligned
+    else:
+        lda, ldb = _ld(K, 3) + 4, _ld(N, 3) + 4
+    ldc = N + 3
     g = np.random.default_rng(M + 3 * N + K)
-    A = orc.pack(32, 2, g.standard_normal(M * lda).astype(np.float32))
-    B = orc.pack(32, 2, g.standard_normal(K * ldb).astype(np.float32))
+    A = orc.pack(32, k, g.standard_normal(M * lda).astype(np.float32))
+    B = orc.pack(32, k, g.standard_normal(K * ldb).astype(np.float32))
     C = torch.full((M * ldc,), 7.0, dtype=torch.float32, device=dev)
-    flyte.gemm((32, 2), (32, 2), (32, 4), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), C=C,
-               lda=lda, ldb=ldb, ldc=ldc)
+    flyte.gemm((32, k), (32, k), (32, 4), M, N, K, torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev), C=C,
+               lda=lda, ldb=ldb, ldc=ldc, flags=flyte.GEMM_ALL_PRODUCTS if case == "four" else 0)
     Ch = C.cpu().numpy().reshape(M, ldc).astype(np.float64)
     assert np.all(Ch[:, N:] == 7.0)
     rows = np.array([0, 1, 255, 256, 4095, 4096, M - 2, M - 1])
@@ -406,8 +416,10 @@ def test_gemm_bf16_large_edges(dev, orc, shape):
     gi, gj = np.meshgrid(rows, cols, indexing="ij")
     ii = np.concatenate([gi.reshape(-1), g.integers(0, M, 512)])
     jj = np.concatenate([gj.reshape(-1), g.integers(0, N, 512)])
-    ce, cab = orc.gemm_entries((32, 2), (32, 2), K, A, lda, B, ldb, ii, jj)
-    assert np.all(np.abs(Ch[ii, jj] - ce) <= gam(K, U32) * cab)
+    ce, cab = orc.gemm_entries((32, k), (32, k), K, A, lda, B, ldb, ii, jj)
+    bound = {"bf16": gam(K, U32), "three": 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2,
+             "four": gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2}[case]
+    assert np.all(np.abs(Ch[ii, jj] - ce) <= bound * cab)
 
 
 @pytest.mark.parametrize("kin,kout", [(5, 5), (6, 8), (8, 3), (3, 7)])
@@ -447,7 +459,7 @@ def pieces_bound(kin, allp, K, ce, cab, kout):
 
 @pytest.mark.parametrize("kin", [2, 3, 4])
 @pytest.mark.parametrize("allp", [False, True])
-@pytest.mark.parametrize("shape", [(256, 256, 128), (300, 264, 133), (384, 256, 64)])
+@pytest.mark.parametrize("shape", [(256, 256, 128), (300, 264, 133), (384, 256, 64), (300, 260, 96)])
 def test_gemm_pieces_all_entries(dev, orc, kin, allp, shape):
     """Rows of A scaled over 2^-300 .. 2^300 and columns of B over 2^-200 .. 2^200
     (each row or column scales as a whole, exactly): every entry within the pieces
