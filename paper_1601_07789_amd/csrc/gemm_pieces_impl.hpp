@@ -101,7 +101,7 @@ __device__ __forceinline__ uint32_t pc_top_pair(uint32_t a, uint32_t b)
 
 struct PcB32K3 {
     static constexpr int KB = 3, PIECES = 2, ROUND_P = 1;
-    static constexpr bool SCALED = false, SPECIALS = true, KMAJOR_B = false;
+    static constexpr bool SCALED = false, SPECIALS = true, KMAJOR_B = false, DWORD_PAIRS = false;
     __device__ static void values(const uint32_t (&d)[3], const int32_t (&)[4], uint32_t (&x)[4])
     {
         unpack_elems<Fmt<32, 3>, 4>(d, x);
@@ -127,7 +127,8 @@ struct PcB32K3 {
 template <int K>
 struct PcB64 {
     static constexpr int KB = K, PIECES = K - 1, ROUND_P = -1;
-    static constexpr bool SCALED = true, SPECIALS = false, KMAJOR_B = true;
+    // K = 2: a loaded dword is one bfloat16 pair (see pc_b64k2_pair)
+    static constexpr bool SCALED = true, SPECIALS = false, KMAJOR_B = true, DWORD_PAIRS = (K == 2);
     __device__ static void values(const uint32_t (&d)[K], const int32_t (&shift)[4], uint32_t (&x)[4])
     {
         uint64_t u[4];
@@ -151,6 +152,31 @@ struct PcB64 {
         return r;
     }
 };
+
+// {64,2}: the dword holding two elements (s, 11-bit e, 4-bit m each, one per half) to
+// the bfloat16 pair of their scaled values, s | (e - e_ref + 127) << 7 | m << 3, in
+// packed 16-bit arithmetic; sub holds (e_ref - 127) << 7 of each half's row or column,
+// mod 2^16.  For a row or column that can be scaled, e - e_ref + 127 lies in [87, 127],
+// so the difference needs no wider arithmetic; zeros keep their sign.  The same bits as
+// the scaled binary32 value's top half.
+typedef unsigned short pc_u16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pc_b64k2_pair(uint32_t d, pc_u16x2_t sub)
+{
+    const uint32_t magw = d & 0x7FFF7FFFu;
+    const pc_u16x2_t mag = __builtin_bit_cast(pc_u16x2_t, magw);
+    const uint32_t v = __builtin_bit_cast(uint32_t, (mag << 3) - sub);
+    // times min(magnitude, 1): 0 for a zero half, 1 otherwise (packed min and
+    // multiply, written as instructions so the compiler keeps the halves packed)
+    uint32_t nz, r;
+    asm("v_pk_min_u16 %0, %1, %2" : "=v"(nz) : "v"(magw), "v"(0x00010001u));
+    asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(v), "v"(nz));
+    return (d & 0x80008000u) | r;
+}
+
+__device__ __forceinline__ unsigned short pc_b64k2_sub(int32_t shift)
+{
+    return (unsigned short)((shift >> 20) * 128);
+}
 
 // piece PC of two values as one bfloat16 pair
 template <class LD, int PC, bool SAFE>
@@ -352,6 +378,31 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     auto store_tiles = [&](int s) {
         uint16_t* As = lds[s];
         uint16_t* Bs = lds[s] + P * A_TILE;
+        if constexpr (LD::DWORD_PAIRS) {
+            // one piece, each loaded dword one pair: A along its chunk, B along the columns
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) {
+                const int c = t + THREADS * i, row = c / (PC_BK / 4), kc = c % (PC_BK / 4);
+                const int ao = row * PC_BK + ((kc >> 1) ^ ((row >> 2) & 3)) * 8 + (kc & 1) * 4;
+                const unsigned short u = pc_b64k2_sub(sa[i][0]);
+                const pc_u16x2_t sub = {u, u};
+                *reinterpret_cast<pc_u32x2*>(As + ao) = pc_u32x2{pc_b64k2_pair(ra[i][0], sub), pc_b64k2_pair(ra[i][1], sub)};
+            }
+#pragma unroll
+            for (int g = 0; g < B_GR; ++g) {
+                const int gi = t + THREADS * g, nc = b_cg(gi) * 4, kg = b_kg(gi);
+                const pc_u16x2_t sub0 = {pc_b64k2_sub(sb[g][0]), pc_b64k2_sub(sb[g][1])};
+                const pc_u16x2_t sub1 = {pc_b64k2_sub(sb[g][2]), pc_b64k2_sub(sb[g][3])};
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int kr = kg * 4 + r, gr = (kr & 3) | ((kr >> 1) & 4);
+                    const int bo = kr * BN + ((nc >> 3) ^ (2 * gr)) * 8 + (nc & 7);
+                    *reinterpret_cast<pc_u32x2*>(Bs + bo) =
+                        pc_u32x2{pc_b64k2_pair(rb[g][r][0], sub0), pc_b64k2_pair(rb[g][r][1], sub1)};
+                }
+            }
+            return;
+        }
         uint32_t xa[A_CH][4], xb[B_GR][4][4];   // values: A [chunk][element], B [group][k-row][column]
 #pragma unroll
         for (int i = 0; i < A_CH; ++i) LD::values(ra[i], sa[i], xa[i]);
