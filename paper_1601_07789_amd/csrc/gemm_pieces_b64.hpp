@@ -11,8 +11,8 @@ template <int K, int PRODS, int OUTK, int RMODE>
 fb_status pc_run_b64(int64_t M, int64_t N, int64_t Kd, const void* A, int64_t lda, const void* B, int64_t ldb,
                             void* C, int64_t ldc, const PcScale& sc, hipStream_t stream)
 {
-    if constexpr (K == 4)   // three pieces: 128 x 128 tiles keep both stages in LDS
-        return pc_run<PcB64<4>, PRODS, 128, 128, 2, 2, OUTK, RMODE>(M, N, Kd, A, lda, B, ldb, C, ldc, sc, stream);
+    if constexpr (K == 4)   // three pieces: 128 x 256 tiles keep both stages in LDS (144 KiB)
+        return pc_run<PcB64<4>, PRODS, 128, 256, 2, 4, OUTK, RMODE>(M, N, Kd, A, lda, B, ldb, C, ldc, sc, stream);
     else
         return pc_run<PcB64<K>, PRODS, 256, 256, 2, 4, OUTK, RMODE>(M, N, Kd, A, lda, B, ldb, C, ldc, sc, stream);
 }
