@@ -44,12 +44,13 @@
 //    special values, and there the k-major layout's extra address registers
 //    cost spills (3-product 383 -> 295 TFLOP/s at 8192^3).
 // The swizzles and the plane offset put the 16 lanes of a read phase (and the
-// 8 k-rows of a transposing read phase) on distinct banks; a store instruction
-// has at most two lanes on one bank per 32-lane phase.
-// Shapes need not be tile multiples: edge tiles and the
-// last K step load with bounds (elements outside the matrix read as +0, and
-// the bytes past a row's last element are never read), and C is stored only
-// inside the matrix.
+// 8 k-rows of a transposing read phase) on distinct banks, and the 32 lanes of
+// a store phase on 64 distinct banks.
+// Shapes need not be tile multiples.  With N a multiple of 4 and K of 32, rows
+// and column groups past the edge load the last valid ones (whole chunks);
+// otherwise edge tiles and the last K step load with bounds (elements outside
+// the matrix read as +0, and the bytes past a row's last element are never
+// read).  C is stored only inside the matrix.
 #pragma once
 
 #include "codec.hpp"
@@ -173,6 +174,7 @@ __device__ __forceinline__ uint32_t pc_b64k2_pair(uint32_t d, pc_u16x2_t sub)
     return (d & 0x80008000u) | r;
 }
 
+// (e_ref - 127) << 7 mod 2^16 of a row or column, from its shift word (e_ref - 127) << 20
 __device__ __forceinline__ unsigned short pc_b64k2_sub(int32_t shift)
 {
     return (unsigned short)((shift >> 20) * 128);
@@ -258,6 +260,7 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     static_assert(KM || BN % 128 == 0, "n-major B groups: 32 column groups per k-row group pair");
     static_assert(STAGE * 2 * 2 <= 160 * 1024, "LDS");
     static_assert(OUTK == 0 || LD::SCALED, "packed binary64 C comes from scaled operands");
+    static_assert(!LD::DWORD_PAIRS || (KM && P == 1 && KB == 2), "dword pairs: one piece of {64,2}, k-major B");
     // The accumulators go to AGPRs (an empty statement that clobbers one makes
     // the compiler place them there), leaving the VGPRs to fragments and loads.
     asm volatile("; accumulators in AGPRs" ::: "a0");
