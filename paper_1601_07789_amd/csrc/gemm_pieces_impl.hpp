@@ -28,7 +28,8 @@
 // Tiling: BM x BN x 32 per workgroup, WGM x WGN waves each (BM/WGM) x
 // (BN/WGN) of v_mfma_f32_16x16x32_bf16 tiles; double-buffered LDS, one
 // barrier per K step, the next step's global loads issued before the current
-// step's MFMAs.  A piece planes are m-major (k contiguous, unpadded; 16-byte
+// step's MFMAs ({64,2}, one product per step: the loads of the step after next
+// issued after a step's LDS stores, before its barrier).  A piece planes are m-major (k contiguous, unpadded; 16-byte
 // chunk c of row R at c ^ ((R >> 2) & 3)), read with ds_read_b128.  Two B
 // layouts, chosen by the loader (KMAJOR_B):
 //  - k-major B (the binary64 pieces): B piece planes k-major as B is stored
@@ -102,7 +103,7 @@ __device__ __forceinline__ uint32_t pc_top_pair(uint32_t a, uint32_t b)
 
 struct PcB32K3 {
     static constexpr int KB = 3, PIECES = 2, ROUND_P = 1;
-    static constexpr bool SCALED = false, SPECIALS = true, KMAJOR_B = false, DWORD_PAIRS = false;
+    static constexpr bool SCALED = false, SPECIALS = true, KMAJOR_B = false, DWORD_PAIRS = false, EARLY_LOADS = false;
     __device__ static void values(const uint32_t (&d)[3], const int32_t (&)[4], uint32_t (&x)[4])
     {
         unpack_elems<Fmt<32, 3>, 4>(d, x);
@@ -128,8 +129,10 @@ struct PcB32K3 {
 template <int K>
 struct PcB64 {
     static constexpr int KB = K, PIECES = K - 1, ROUND_P = -1;
-    // K = 2: a loaded dword is one bfloat16 pair (see pc_b64k2_pair)
-    static constexpr bool SCALED = true, SPECIALS = false, KMAJOR_B = true, DWORD_PAIRS = (K == 2);
+    // K = 2: a loaded dword is one bfloat16 pair (see pc_b64k2_pair), and with one product
+    // per step the loads of the step after next are issued before each barrier
+    static constexpr bool SCALED = true, SPECIALS = false, KMAJOR_B = true, DWORD_PAIRS = (K == 2),
+                          EARLY_LOADS = (K == 2);
     __device__ static void values(const uint32_t (&d)[K], const int32_t (&shift)[4], uint32_t (&x)[4])
     {
         uint64_t u[4];
@@ -537,17 +540,32 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
 
     // the last K step is peeled so the loop body has no branches on it
     const int KT = (K + PC_BK - 1) / PC_BK;
-    load_tiles(0);
-    store_tiles(0);
-    __syncthreads();
-    for (int kt = 0; kt < KT - 1; ++kt) {
-        const int s = kt & 1;
-        load_tiles((kt + 1) * PC_BK);
-        // the next step's global loads stay ahead of this step's MFMAs
-        __builtin_amdgcn_sched_barrier(0);
-        compute(s);
-        store_tiles(s ^ 1);
+    if constexpr (LD::EARLY_LOADS) {
+        load_tiles(0);
+        store_tiles(0);
+        if (KT > 1) load_tiles(PC_BK);
         __syncthreads();
+        for (int kt = 0; kt < KT - 1; ++kt) {
+            const int s = kt & 1;
+            compute(s);
+            store_tiles(s ^ 1);
+            // the loads of the step after next are issued before the barrier
+            if (kt + 2 < KT) load_tiles((kt + 2) * PC_BK);
+            __syncthreads();
+        }
+    } else {
+        load_tiles(0);
+        store_tiles(0);
+        __syncthreads();
+        for (int kt = 0; kt < KT - 1; ++kt) {
+            const int s = kt & 1;
+            load_tiles((kt + 1) * PC_BK);
+            // the next step's global loads stay ahead of this step's MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+            compute(s);
+            store_tiles(s ^ 1);
+            __syncthreads();
+        }
     }
     compute((KT - 1) & 1);
 

@@ -459,7 +459,7 @@ def pieces_bound(kin, allp, K, ce, cab, kout):
 
 @pytest.mark.parametrize("kin", [2, 3, 4])
 @pytest.mark.parametrize("allp", [False, True])
-@pytest.mark.parametrize("shape", [(256, 256, 128), (300, 264, 133), (384, 256, 64), (300, 260, 96)])
+@pytest.mark.parametrize("shape", [(256, 256, 128), (300, 264, 133), (384, 256, 64), (300, 260, 96), (129, 256, 20)])
 def test_gemm_pieces_all_entries(dev, orc, kin, allp, shape):
     """Rows of A scaled over 2^-300 .. 2^300 and columns of B over 2^-200 .. 2^200
     (each row or column scales as a whole, exactly): every entry within the pieces
