@@ -505,7 +505,7 @@ def test_gemm_pieces_integer_data_bit_exact(dev, orc, kin):
             assert np.array_equal(C if kout < 8 else C.view(np.uint8), want), (flags, kout)
 
 
-@pytest.mark.parametrize("kin", [3, 4])
+@pytest.mark.parametrize("kin", [2, 3, 4])
 def test_gemm_pieces_fallback_bands(dev, orc, kin):
     """Rows and columns that cannot be scaled exactly -- an element 2^-60 below its
     row's largest, a binary64 subnormal, an infinity, a NaN -- send every 128 x 128
@@ -519,7 +519,8 @@ def test_gemm_pieces_fallback_bands(dev, orc, kin):
     Av = g.standard_normal((M, K))
     Bv = g.standard_normal((K, N))
     Av[5, 3] *= 2.0 ** -60          # row band 0 of A: spread above 2^40
-    Av[300, 7] = 5e-310             # row band 2: a binary64 subnormal
+    # row band 2: a binary64 subnormal ({64,2} keeps 4 fraction bits, so one near 2^-1022)
+    Av[300, 7] = 2e-308 if kin == 2 else 5e-310
     Bv[9, 200] = np.inf             # column band 1 of B: infinity
     Bv[20, 450] = np.nan            # column band 3: NaN
     A, B = orc.pack(64, kin, Av.reshape(-1)), orc.pack(64, kin, Bv.reshape(-1))
