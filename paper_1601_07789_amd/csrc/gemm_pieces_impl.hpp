@@ -47,11 +47,12 @@
 // The swizzles and the plane offset put the 16 lanes of a read phase (and the
 // 8 k-rows of a transposing read phase) on distinct banks, and the 32 lanes of
 // a store phase on 64 distinct banks.
-// Shapes need not be tile multiples.  With N a multiple of 4 and K of 32, rows
-// and column groups past the edge load the last valid ones (whole chunks);
-// otherwise edge tiles and the last K step load with bounds (elements outside
-// the matrix read as +0, and the bytes past a row's last element are never
-// read).  C is stored only inside the matrix.
+// Shapes need not be tile multiples.  Rows past M load the last row; with N a
+// multiple of 4, column groups past N load the last one (whole chunks),
+// otherwise the column groups that reach past N load with bounds; a partial
+// last K step, peeled out of the loop, loads with bounds (elements outside the
+// matrix read as +0, and the bytes past a row's last element are never read).
+// C is stored only inside the matrix.
 #pragma once
 
 #include "codec.hpp"
@@ -237,11 +238,13 @@ __device__ __forceinline__ uint64_t pc_shfl_u64(uint64_t v, int src)
 // PRODS: bit (pa * P + pb) set = form the product of A piece pa and B piece pb.
 // OUTK = 0: C is FP32 (binary32 operands); else C is packed binary64 in OUTK
 // bytes, rounded in mode RMODE (scaled operands).
-// EDGE 0: M, N are multiples of BM, BN and K of 32.  EDGE 1: any M, N with N a
-// multiple of 4 and K of 32; rows past M and column groups past N load the
-// last row / column group (whole chunks, so no element of a valid column
-// moves), and C is stored only inside the matrix.  EDGE 2: any M, N, K; loads
-// of edge tiles and of a partial last K step are bounded.
+// EDGE 0: M, N are multiples of BM, BN and K of 32.  EDGE 1: any M, K with N a
+// multiple of 4; rows past M and column groups past N load the last row /
+// column group (whole chunks, so no element of a valid column moves), a
+// partial last K step loads with bounds, and C is stored only inside the
+// matrix.  EDGE 2: any M, N, K and leading dimensions; rows past M load the
+// last row, B column groups that reach past N and a partial last K step load
+// with bounds, addresses in 64 bits.
 template <class LD, int PRODS, int BM, int BN, int WGM, int WGN, int OUTK, int RMODE, int EDGE>
 __global__ void __launch_bounds__(64 * WGM * WGN)
 k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict__ B, int64_t ldb,
@@ -302,10 +305,11 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
         return 2 * ((gi / 64) / (BN / 128)) + (gi / 16) % 2;
     };
 
-    // tile row of A chunk c and first tile column of B group gi, as loaded (EDGE 1: clamped)
+    // tile row of A chunk c and first tile column of B group gi, as loaded (rows clamped
+    // in EDGE 1 and 2, column groups in EDGE 1)
     auto a_row = [&](int c) {
         const int r = c / (PC_BK / 4);
-        return EDGE == 1 ? pc_min(m0 + r, M - 1) - m0 : r;
+        return EDGE >= 1 ? pc_min(m0 + r, M - 1) - m0 : r;
     };
     auto b_col = [&](int gi) {
         const int cc = b_cg(gi) * 4;
@@ -349,9 +353,28 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
     const uint8_t* Atile = A + (int64_t)m0 * lda * KB;
     const uint8_t* Btile = B + (int64_t)n0 * KB;
 
-    auto load_tiles = [&](int k0) {
-        const bool edge = EDGE == 2 && (!interior || k0 + PC_BK > K);
-        if (!edge) {
+    // a whole K step (k0 + 32 <= K)
+    auto load_full = [&](int k0) {
+        if constexpr (EDGE == 2) {
+            // 64-bit addresses (the leading dimensions need not keep tile offsets
+            // within 31 bits); A rows past M load the last row, and only B column
+            // groups that reach past N load with bounds (those past it read nothing)
+#pragma unroll
+            for (int i = 0; i < A_CH; ++i) {
+                const int c = t + THREADS * i, row = m0 + a_row(c), kk = k0 + (c % (PC_BK / 4)) * 4;
+                load_dwords(reinterpret_cast<const uint32_t*>(A + ((int64_t)row * lda + kk) * KB), ra[i]);
+            }
+#pragma unroll
+            for (int g = 0; g < B_GR; ++g) {
+                const int gi = t + THREADS * g, col = n0 + b_cg(gi) * 4, kr = k0 + b_kg(gi) * 4;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const uint8_t* p = B + ((int64_t)(kr + r) * ldb + col) * KB;
+                    if (col + 4 <= N) load_dwords(reinterpret_cast<const uint32_t*>(p), rb[g][r]);
+                    else pc_load_edge<KB>(p, pc_max(0, N - col) * KB, rb[g][r]);
+                }
+            }
+        } else {
             const uint8_t* Ak = Atile + k0 * KB;
             const uint8_t* Bk = Btile + (int64_t)k0 * ldb * KB;
 #pragma unroll
@@ -360,8 +383,10 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
             for (int g = 0; g < B_GR; ++g)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) load_dwords(reinterpret_cast<const uint32_t*>(Bk + boff[g][r]), rb[g][r]);
-            return;
         }
+    };
+    // a partial last K step (EDGE 1 and 2): every load bounded
+    auto load_bounded = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < A_CH; ++i) {
             const int c = t + THREADS * i, row = m0 + c / (PC_BK / 4), kk = k0 + (c % (PC_BK / 4)) * 4;
@@ -538,29 +563,42 @@ k_gemm_pc(const uint8_t* __restrict__ A, int64_t lda, const uint8_t* __restrict_
         __builtin_amdgcn_s_setprio(0);
     };
 
-    // the last K step is peeled so the loop body has no branches on it
-    const int KT = (K + PC_BK - 1) / PC_BK;
+    // KF whole K steps, then (EDGE 1 and 2) a partial one; the bounded loads of the
+    // partial step stay out of the loop body
+    const int KF = K / PC_BK, KT = (K + PC_BK - 1) / PC_BK;
+    auto load_step = [&](int kt) {
+        if (EDGE == 0 || kt < KF) load_full(kt * PC_BK);
+        else load_bounded(kt * PC_BK);
+    };
     if constexpr (LD::EARLY_LOADS) {
-        load_tiles(0);
+        load_step(0);
         store_tiles(0);
-        if (KT > 1) load_tiles(PC_BK);
+        if (KT > 1) load_step(1);
         __syncthreads();
         for (int kt = 0; kt < KT - 1; ++kt) {
             const int s = kt & 1;
             compute(s);
             store_tiles(s ^ 1);
             // the loads of the step after next are issued before the barrier
-            if (kt + 2 < KT) load_tiles((kt + 2) * PC_BK);
+            if (kt + 2 < KT) load_step(kt + 2);
             __syncthreads();
         }
     } else {
-        load_tiles(0);
+        load_step(0);
         store_tiles(0);
         __syncthreads();
-        for (int kt = 0; kt < KT - 1; ++kt) {
+        for (int kt = 0; kt < KF - 1; ++kt) {
             const int s = kt & 1;
-            load_tiles((kt + 1) * PC_BK);
+            load_full((kt + 1) * PC_BK);
             // the next step's global loads stay ahead of this step's MFMAs
+            __builtin_amdgcn_sched_barrier(0);
+            compute(s);
+            store_tiles(s ^ 1);
+            __syncthreads();
+        }
+        if (EDGE != 0 && KT > KF && KF > 0) {
+            const int s = (KF - 1) & 1;
+            load_bounded(KF * PC_BK);
             __builtin_amdgcn_sched_barrier(0);
             compute(s);
             store_tiles(s ^ 1);
@@ -634,15 +672,15 @@ fb_status pc_run(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, co
     auto a = static_cast<const uint8_t*>(A);
     auto b = static_cast<const uint8_t*>(B);
     // shapes that are tile multiples take the instance without bounds, those
-    // with N a multiple of 4 and K of 32 the clamped one (both need per-tile
-    // offsets that fit 31 bits), the rest the bounded one
+    // with N a multiple of 4 the clamped one (both need per-tile offsets that
+    // fit 31 bits), the rest the bounded one
     constexpr int KB = LD::KB;
     const bool offs = (int64_t)BM * lda * KB < (1ll << 31) && (int64_t)PC_BK * ldb * KB < (1ll << 31);
     const unsigned grid = (unsigned)blocks, threads = 64 * WGM * WGN;
     if (offs && M % BM == 0 && N % BN == 0 && K % PC_BK == 0)
         k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, 0><<<grid, threads, 0, stream>>>(
             a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
-    else if (offs && N % 4 == 0 && K % PC_BK == 0)
+    else if (offs && N % 4 == 0)
         k_gemm_pc<LD, PRODS, BM, BN, WGM, WGN, OUTK, RMODE, 1><<<grid, threads, 0, stream>>>(
             a, lda, b, ldb, C, ldc, (int)M, (int)N, (int)K, sc);
     else

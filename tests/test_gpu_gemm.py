@@ -386,12 +386,13 @@ def test_gemm_ragged_binary32(dev, orc, case, shape):
 
 @pytest.mark.parametrize("case,shape", [("bf16", (4100, 4104, 333)), ("bf16", (4097, 4099, 70)),
                                         ("three", (4100, 4104, 320)), ("four", (4100, 4104, 320)),
-                                        ("three", (4097, 4099, 70))])
+                                        ("three", (4097, 4099, 70)), ("four", (4100, 4104, 333))])
 def test_gemm_bf16_large_edges(dev, orc, case, shape):
     """Shapes large enough for 256 x 256 tiles that are not tile multiples.  {32,2}:
     N a multiple of 8 (rows and column chunks clamped, partial last K step) and N
-    not (the chunk N cuts read by elements).  {32,3}: N a multiple of 4 and K of 32
-    (rows and column groups clamped) and neither (bounded loads).  Entries of the
+    not (the chunk N cuts read by elements).  {32,3}: N a multiple of 4 (rows and
+    column groups clamped, with and without a partial last K step) and neither
+    (bounded column groups past N, 64-bit addresses).  Entries of the
     edge rows and columns and random ones within the bound, C's padding columns
     untouched."""
     import torch
@@ -420,6 +421,28 @@ def test_gemm_bf16_large_edges(dev, orc, case, shape):
     bound = {"bf16": gam(K, U32), "three": 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2,
              "four": gam(4 * K, U32) * (1 + 2.0 ** -7) ** 2}[case]
     assert np.all(np.abs(Ch[ii, jj] - ce) <= bound * cab)
+
+
+def test_gemm_three_product_huge_lda(dev, orc):
+    """{32,3} with a leading dimension so large (6M elements, 18 MB per row) that
+    byte offsets within a 256-row tile pass 2^32: the bounded instance addresses
+    in 64 bits.  Every entry within the 3-product bound."""
+    import torch
+    M, N, K, lda = 300, 260, 96, 6_000_000
+    log(f"gemm three huge lda {M}x{N}x{K} lda={lda}")
+    g = np.random.default_rng(91)
+    Ac = orc.pack(32, 3, g.standard_normal(M * K).astype(np.float32))
+    ldb = _ld(N, 3)
+    B = orc.pack(32, 3, g.standard_normal(K * ldb).astype(np.float32))
+    Ad = torch.zeros(M * lda * 3, dtype=torch.uint8, device=dev)
+    Ad.view(M, lda * 3)[:, :K * 3] = torch.from_numpy(Ac).to(dev).view(M, K * 3)
+    C = flyte.gemm((32, 3), (32, 3), (32, 4), M, N, K, Ad, torch.from_numpy(B).to(dev), lda=lda, ldb=ldb)
+    Ch = C.cpu().numpy().reshape(M, N).astype(np.float64)
+    del Ad
+    ii, jj = all_entries(M, N)
+    ce, cab = orc.gemm_entries((32, 3), (32, 3), K, Ac, K, B, ldb, ii, jj)
+    bound = 2.0 ** -14 + gam(3 * K, U32) * (1 + 2.0 ** -7) ** 2
+    assert np.all(np.abs(Ch.reshape(-1) - ce) <= bound * cab)
 
 
 @pytest.mark.parametrize("kin,kout", [(5, 5), (6, 8), (8, 3), (3, 7)])
